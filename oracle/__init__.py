@@ -1,0 +1,174 @@
+"""CPU oracle for the tile-partitioned GEMM  C = A.B  (binary64, plain loops).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code
+with the HIP path and never imports it.
+
+What it computes (arxiv 2606.15991):
+  * gemm / gemm_scaled / gemm_entries -- the plain definition of the
+    product that the mapped-partition GEMM of Sec. 3.6 reaches: every owned
+    output tile is a zero-initialised sum of tile products over K, stored
+    once, i.e. R[i,j] = sum_k A[i,k] B[k,j].  Quantised (FP8) operands are
+    decoded exactly and the per-row / per-column scales are applied to the
+    binary64 sum.
+  * rel_fro -- relative Frobenius error in binary64.
+  * partition_paint -- the ownership rules of Sec. 3.4 and App. A
+    (injective program -> sub-tensor map, covering grid) checked by painting
+    every output element.
+  * decode_bf16 / decode_e4m3fn -- exact decoding of the two 16/8-bit
+    element formats from their published bit layouts.
+  * mlp (submodule) -- binary64 forward/backward of the tile-picker MLP and
+    its Adam update.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i64 = ctypes.c_int64
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    lib.oracle_gemm.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp, _i64,
+                                ctypes.c_int, _dp, _i64]
+    lib.oracle_gemm.restype = None
+    lib.oracle_gemm_scaled.argtypes = [_i64, _i64, _i64, _dp, _i64, _dp,
+                                       _i64, ctypes.c_int, _dp, _dp, _dp,
+                                       _i64]
+    lib.oracle_gemm_scaled.restype = None
+    lib.oracle_gemm_entries.argtypes = [_i64, _dp, _i64, _dp, _i64,
+                                        ctypes.c_int, _dp, _dp,
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        _i64, _dp]
+    lib.oracle_gemm_entries.restype = None
+    lib.oracle_rel_fro.argtypes = [_dp, _dp, _i64]
+    lib.oracle_rel_fro.restype = ctypes.c_double
+    lib.oracle_partition_paint.argtypes = [_i64, _i64, _i64, _i64, _i64,
+                                           ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]
+    lib.oracle_partition_paint.restype = ctypes.c_int
+    lib.oracle_ranges_intersect.argtypes = [ctypes.c_uint64] * 4
+    lib.oracle_ranges_intersect.restype = ctypes.c_int
+    lib.oracle_decode_bf16.argtypes = [ctypes.c_void_p, _dp, _i64]
+    lib.oracle_decode_bf16.restype = None
+    lib.oracle_decode_e4m3fn.argtypes = [ctypes.c_void_p, _dp, _i64]
+    lib.oracle_decode_e4m3fn.restype = None
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def decode_bf16(bits) -> np.ndarray:
+    """bfloat16 bit patterns (any integer array of 16-bit codes) -> float64."""
+    b = np.ascontiguousarray(np.asarray(bits).astype(np.uint16))
+    out = np.empty(b.shape, dtype=np.float64)
+    _load().oracle_decode_bf16(b.ctypes.data, out.ctypes.data_as(_dp), b.size)
+    return out
+
+
+def decode_e4m3fn(codes) -> np.ndarray:
+    """OCP E4M3 (e4m3fn) byte codes -> float64 (NaN for S.1111.111)."""
+    b = np.ascontiguousarray(np.asarray(codes).astype(np.uint8))
+    out = np.empty(b.shape, dtype=np.float64)
+    _load().oracle_decode_e4m3fn(b.ctypes.data, out.ctypes.data_as(_dp),
+                                 b.size)
+    return out
+
+
+def gemm(A, B, b_nk: bool = False, sa=None, sb=None) -> np.ndarray:
+    """R = diag(sa) . A . B . diag(sb) in binary64.
+
+    A: (M, K).  B: (K, N), or (N, K) when b_nk.  sa: (M,) or None,
+    sb: (N,) or None.
+    """
+    A, pa = _f64(A)
+    B, pb = _f64(B)
+    M, K = A.shape
+    N = B.shape[0] if b_nk else B.shape[1]
+    assert (B.shape[1] if b_nk else B.shape[0]) == K
+    R = np.empty((M, N), dtype=np.float64)
+    lib = _load()
+    if sa is None and sb is None:
+        lib.oracle_gemm(M, N, K, pa, K, pb, B.shape[1], int(b_nk),
+                        R.ctypes.data_as(_dp), N)
+    else:
+        sa_a, psa = _f64(sa) if sa is not None else (None, None)
+        sb_a, psb = _f64(sb) if sb is not None else (None, None)
+        lib.oracle_gemm_scaled(M, N, K, pa, K, pb, B.shape[1], int(b_nk),
+                               psa, psb, R.ctypes.data_as(_dp), N)
+    return R
+
+
+def gemm_entries(A, B, ii, jj, b_nk: bool = False, sa=None,
+                 sb=None) -> np.ndarray:
+    """Entries R[ii[t], jj[t]] of diag(sa) . A . B . diag(sb)."""
+    A, pa = _f64(A)
+    B, pb = _f64(B)
+    K = A.shape[1]
+    ii = np.ascontiguousarray(ii, dtype=np.int64)
+    jj = np.ascontiguousarray(jj, dtype=np.int64)
+    out = np.empty(ii.shape, dtype=np.float64)
+    sa_a, psa = _f64(sa) if sa is not None else (None, None)
+    sb_a, psb = _f64(sb) if sb is not None else (None, None)
+    _load().oracle_gemm_entries(K, pa, K, pb, B.shape[1], int(b_nk), psa, psb,
+                                ii.ctypes.data, jj.ctypes.data, ii.size,
+                                out.ctypes.data_as(_dp))
+    return out
+
+
+def rel_fro(C, R) -> float:
+    """||C - R||_F / ||R||_F in binary64 (||C||_F when R is all zero)."""
+    C, pc = _f64(C)
+    R, pr = _f64(R)
+    assert C.size == R.size
+    return float(_load().oracle_rel_fro(pc, pr, C.size))
+
+
+PART_OK, PART_ARG, PART_OVERLAP, PART_NOCOVER = 0, 1, 4, 5
+
+
+def partition_paint(M, N, bm, bn, prog_offsets=None, prog_tiles=None):
+    """Paint an M x N output with per-element owner counts.
+
+    Returns (status, counts) where status is PART_OK, PART_OVERLAP,
+    PART_NOCOVER or PART_ARG.  With no map, one program per sub-tensor.
+    """
+    counts = np.zeros((max(M, 0), max(N, 0)), dtype=np.int32)
+    if prog_offsets is None:
+        st = _load().oracle_partition_paint(M, N, bm, bn, 0, None, None,
+                                            counts.ctypes.data)
+    else:
+        po = np.ascontiguousarray(prog_offsets, dtype=np.int32)
+        pt = np.ascontiguousarray(prog_tiles, dtype=np.int32)
+        if pt.size == 0:
+            pt = np.zeros(1, dtype=np.int32)
+        st = _load().oracle_partition_paint(M, N, bm, bn, po.size - 1,
+                                            po.ctypes.data, pt.ctypes.data,
+                                            counts.ctypes.data)
+    return int(st), counts
+
+
+def ranges_intersect(a: int, na: int, b: int, nb: int) -> bool:
+    return bool(_load().oracle_ranges_intersect(a, na, b, nb))
