@@ -1,0 +1,286 @@
+#!/usr/bin/env python3
+"""Benchmark of the tile-partitioned GEMM hot path on one MI355X.
+
+Headline: BF16 GEMM M = N = K = 8192 (entries N(0,1) rounded to bf16, binary32
+accumulation and output, C split into 256 x 256 sub-tensors, one persistent
+launch of tile programs).  One step = one tile_gemm launch over the resident
+inputs.  Prints ONE JSON line with TFLOP/s, the roofline fraction of the
+dominant kernel, the error against the oracle on sampled rows, the oracle's
+own CPU rate on those rows, and secondary measurements (FP8, FP32, split
+precision, decode-shaped GB/s, grouped launch).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = ("GEMM TFLOP/s & %MFMA peak (bf16/fp8 vs fp32) at stated err; "
+          "M=1 GB/s")
+PEAK_TFLOPS = {"bf16": 2516.6, "fp8": 5033.2, "f32": 157.3}
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, warmup):
+    """Average ms per call of fn over `steps` calls on the current stream,
+    bracketed by device synchronisation, after `warmup` untimed calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def exact64(t):
+    import oracle
+    t = t.detach().cpu().contiguous()
+    if t.dtype == torch.bfloat16:
+        return oracle.decode_bf16(t.view(torch.int16).numpy().view(np.uint16))
+    if t.dtype == torch.float8_e4m3fn:
+        return oracle.decode_e4m3fn(t.view(torch.uint8).numpy())
+    return t.numpy().astype(np.float64)
+
+
+def oracle_rows(A, B, rows, b_nk=False, sa=None, sb=None, target_s=10.0):
+    """Oracle product of a seeded sample of rows, timed.  Starts with a few
+    rows and grows the sample toward about target_s seconds of CPU work."""
+    import oracle
+    a, b = exact64(A), exact64(B)
+    sa64 = None if sa is None else exact64(sa)
+    sb64 = None if sb is None else exact64(sb)
+    done, secs, R = [], 0.0, []
+    n = 2
+    i = 0
+    while i < len(rows):
+        take = rows[i:i + n]
+        t0 = time.perf_counter()
+        R.append(oracle.gemm(a[take], b, b_nk=b_nk,
+                             sa=None if sa64 is None else sa64[take],
+                             sb=sb64))
+        secs += time.perf_counter() - t0
+        done.extend(take)
+        i += n
+        if secs >= target_s:
+            break
+        n = min(n * 2, len(rows) - i) if i < len(rows) else n
+    return np.asarray(done), np.concatenate(R, axis=0), secs
+
+
+def bench_bf16_main(args, tg):
+    M = N = K = 8192
+    log("bf16 8192^3: generating inputs")
+    A = synth.to_bf16(synth.normal((M, K), 2))
+    B = synth.to_bf16(synth.normal((K, N), 202))
+    Ad, Bd = A.cuda(), B.cuda()
+    C = torch.empty((M, N), device="cuda")
+
+    def step():
+        tg.tile_gemm(Ad, Bd, C, 256, 256)
+
+    log("bf16 8192^3: timing")
+    ms = timed(step, args.steps, args.warmup)
+    flops = 2.0 * M * N * K
+    tflops = flops / (ms * 1e-3) / 1e12
+    # unchecked twin: same kernel, partition check skipped on the host
+    ms_unchecked = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256,
+                                              checked=False),
+                         max(args.steps // 2, 5), 2)
+    step()
+    torch.cuda.synchronize()
+    Cc = C.cpu().numpy()
+    res = {"M": M, "N": N, "K": K, "ms": ms, "tflops": tflops,
+           "ms_unchecked": ms_unchecked, "A": A, "B": B, "C": Cc}
+    return res
+
+
+def cpu_baseline_and_err(res, target_s):
+    import oracle
+    rng = np.random.default_rng(2)
+    rows = rng.permutation(res["M"])[:512]
+    done, R, secs = oracle_rows(res["A"], res["B"], rows, target_s=target_s)
+    got = res["C"][done].astype(np.float64)
+    err = oracle.rel_fro(got, R)
+    flops = 2.0 * len(done) * res["N"] * res["K"]
+    cpu = {"value": flops / secs / 1e12, "unit": "TFLOP/s",
+           "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{len(done)} seeded rows of the 8192^3 bf16 product "
+                     f"({secs:.1f} s)"}
+    return err, cpu, len(done)
+
+
+def bench_fp8(args, tg, n=8192):
+    log(f"fp8 {n}^3")
+    qa, sa = synth.quant_e4m3_rows(synth.normal((n, n), 5))
+    qb, sb = synth.quant_e4m3_rows(synth.normal((n, n), 505))
+    Ad, Bd, sad, sbd = qa.cuda(), qb.cuda(), sa.cuda(), sb.cuda()
+    C = torch.empty((n, n), device="cuda")
+    ms = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True,
+                                    scale_a=sad, scale_b=sbd), 10, 2)
+    return {"M": n, "N": n, "K": n, "ms": ms,
+            "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
+            "frac_fp8_peak": 2.0 * n ** 3 / (ms * 1e-3) / 1e12 /
+            PEAK_TFLOPS["fp8"]}
+
+
+def bench_f32_and_split(args, tg, n=8192):
+    log(f"f32 / split {n}^3")
+    A = synth.normal((n, n), 2).cuda()
+    B = synth.normal((n, n), 202).cuda()
+    C = torch.empty((n, n), device="cuda")
+    out = {}
+    ms = timed(lambda: tg.tile_gemm(A, B, C, 128, 128), 3, 1)
+    out["f32_ms"] = ms
+    out["f32_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    for prec in ("bf16x3", "bf16x6"):
+        ws = torch.empty(tg.tile_gemm_workspace_size(A, B, C,
+                                                     precision=prec),
+                         dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256, precision=prec,
+                                        workspace=ws), 3, 1)
+        out[prec + "_ms"] = ms
+        out[prec + "_eff_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        del ws
+    return out
+
+
+def bench_decode(args, tg):
+    out = []
+    for wdt in ("bf16", "fp8"):
+        for (N, K) in synth.DECODE_SHAPES:
+            for M in (1, 8):
+                x = synth.to_bf16(synth.normal((M, K), 3)).cuda()
+                w = synth.normal((N, K), 303, std=0.02)
+                if wdt == "bf16":
+                    W, s = synth.to_bf16(w), None
+                else:
+                    W, s = synth.quant_e4m3_rows(w)
+                W = W.cuda()
+                s = None if s is None else s.cuda()
+                wbytes = W.numel() * W.element_size()
+                copies = max(2, int(np.ceil(1.0e9 / wbytes)))
+                Ws = [W] + [W.clone() for _ in range(copies - 1)]
+                y = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
+                it = [0]
+
+                def step():
+                    tg.tile_gemm(x, Ws[it[0] % copies], y, b_trans=True,
+                                 scale_b=s)
+                    it[0] += 1
+                reps = max(copies * 4, 40)
+                ms = timed(step, reps, copies)
+                ms_warm = timed(lambda: tg.tile_gemm(x, W, y, b_trans=True,
+                                                     scale_b=s), 40, 5)
+                nbytes = wbytes + (N * 4 if s is not None else 0) + \
+                    2 * M * K + 2 * M * N
+                out.append({"w": wdt, "M": M, "N": N, "K": K,
+                            "us": ms * 1e3, "gbs": nbytes / (ms * 1e-3) / 1e9,
+                            "gbs_warm": nbytes / (ms_warm * 1e-3) / 1e9})
+                log("decode", out[-1])
+                del Ws, W
+    return out
+
+
+def bench_grouped(args, tg):
+    shapes = synth.grouped_shapes(4, 64)
+    log("grouped: 64 problems")
+    As = [synth.to_bf16(synth.normal((m, k), 1000 + i)).cuda()
+          for i, (m, n, k) in enumerate(shapes)]
+    Bs = [synth.to_bf16(synth.normal((k, n), 2000 + i)).cuda()
+          for i, (m, n, k) in enumerate(shapes)]
+    Cs = [torch.empty((m, n), device="cuda") for m, n, k in shapes]
+    launch = tg.tile_gemm_grouped_prepare(As, Bs, Cs,
+                                          config={"bm": 256, "bn": 256})
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    tg.tile_gemm_grouped(launch)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tg.tile_gemm_grouped(launch, stream=s)
+    torch.cuda.synchronize()
+    ms = timed(g.replay, 20, 3)
+    flops = sum(2.0 * m * n * k for m, n, k in shapes)
+    bound = sum(max(2.0 * m * n * k / (PEAK_TFLOPS["bf16"] * 1e12),
+                    (2 * (m * k + k * n) + 4 * m * n) / (PEAK_HBM_GBS * 1e9))
+                for m, n, k in shapes)
+    return {"problems": 64, "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+            "frac_of_roofline_sum": bound / (ms * 1e-3)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true",
+                    help="headline workload only")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
+              "supported by this single-GPU build", file=sys.stderr)
+        sys.exit(2)
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    import paper_2606_15991_amd as tg
+
+    res = bench_bf16_main(args, tg)
+    extra = {"ms_unchecked_launch": res["ms_unchecked"]}
+    if not args.quick:
+        extra["fp8_8192"] = bench_fp8(args, tg)
+        extra.update(bench_f32_and_split(args, tg))
+        extra["decode"] = bench_decode(args, tg)
+        extra["grouped"] = bench_grouped(args, tg)
+    err, cpu, nrows = cpu_baseline_and_err(res, args.cpu_seconds)
+    tflops = res["tflops"]
+    line = {
+        "metric": METRIC,
+        "value": round(tflops, 2),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "bf16 GEMM M=N=K=8192, N(0,1) inputs, "
+                               "f32 accumulate+output, C partition 256x256",
+                   "M": 8192, "N": 8192, "K": 8192,
+                   "partition": [256, 256], "parallelism": "none"},
+        "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
+                     "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                     "frac": round(tflops / PEAK_TFLOPS["bf16"], 4),
+                     "traffic": None},
+        "err_rel_fro": err,
+        "err_rows": nrows,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

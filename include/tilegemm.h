@@ -1,0 +1,255 @@
+/*
+ * tilegemm.h -- C ABI of the MI355X (gfx950) tile-partitioned GEMM library.
+ *
+ * The library computes C = A . B with the tile model of arxiv 2606.15991
+ * ("Fearless Concurrency on the GPU"):
+ *   - the mutable output C is split, before launch, into disjoint BM x BN
+ *     sub-tensors (Sec. 3.4, "Partitioning and Ordering");
+ *   - a grid of tile programs is derived from that partition; with the
+ *     persistent ("mapped partition") schedule of Sec. 3.6 each program owns
+ *     a bounded sequence of sub-tensors, the program -> sub-tensor map is
+ *     injective, and a program stores only into the sub-tensors it owns;
+ *   - the inputs A and B are shared, immutable and never written
+ *     (the &Tensor parameters of the launch-boundary type grammar, Sec. 3.1);
+ *   - every owned sub-tensor starts from a zero accumulator, sums tile
+ *     products over K, and is stored exactly once (Listing "GEMM using
+ *     bounded output sub-tensor indices", Sec. 3.6).
+ *
+ * Conventions shared by every call:
+ *   - Matrices are row-major with a leading dimension `ld` (elements between
+ *     the starts of consecutive rows, ld >= cols).  A matrix occupies the
+ *     bytes [data, data + ((rows-1)*ld + cols) * element_size).
+ *   - Pointers named "device" are HIP device pointers (hipMalloc or
+ *     torch.cuda memory); "host" pointers are ordinary process memory.
+ *   - Ownership (Sec. 3.3, prepare/recover protocol): the library never
+ *     frees, retains or reallocates a caller pointer.  Inputs are borrowed
+ *     read-only.  Outputs, scales and workspaces are exclusively borrowed
+ *     from the call until `stream` reaches the end of the enqueued work; the
+ *     caller must not read, write or free them before synchronising that
+ *     stream (the unsafe-while-in-flight rule of Sec. 3.2).
+ *   - Errors: every argument is validated on the host before anything is
+ *     enqueued.  On any error status nothing has been enqueued and outputs
+ *     are untouched.  tg_last_error() returns a thread-local message for the
+ *     last failing call.  Asynchronous device faults surface at the caller's
+ *     stream synchronisation, not through these calls.
+ *   - No launch call allocates device memory or synchronises the stream, so
+ *     every launch call may be captured into a HIP graph (graph nodes must
+ *     be non-allocating, Sec. 3.2 "CUDA graphs").
+ */
+#ifndef TILEGEMM_H
+#define TILEGEMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* A hipStream_t; 0 is the legacy default stream. */
+typedef void *tg_stream;
+
+typedef enum tg_status {
+    TG_OK = 0,
+    TG_E_ARG = 1,         /* NULL pointer, non-positive size, bad enum value */
+    TG_E_DTYPE = 2,       /* dtype combination not provided                  */
+    TG_E_SHAPE = 3,       /* A.cols != K, C not M x N, ld < cols, ...        */
+    TG_E_OVERLAP = 4,     /* a sub-tensor owned by two programs, or two
+                             outputs of one launch share bytes               */
+    TG_E_NOCOVER = 5,     /* a sub-tensor of the grid is owned by nobody     */
+    TG_E_ALIAS = 6,       /* an output shares bytes with an input            */
+    TG_E_WORKSPACE = 7,   /* workspace missing, too small or misaligned      */
+    TG_E_UNSUPPORTED = 8, /* valid request with no kernel (e.g. a config
+                             that is not instantiated, misaligned vectors)  */
+    TG_E_HIP = 9          /* the HIP runtime reported an error              */
+} tg_status;
+
+typedef enum tg_dtype {
+    TG_F32 = 0,           /* IEEE binary32                                   */
+    TG_BF16 = 1,          /* bfloat16                                        */
+    TG_FP8_E4M3 = 2       /* OCP FP8 E4M3 ("e4m3fn", max 448, no inf)        */
+} tg_dtype;
+
+/* Arithmetic of the contraction.  Accumulation is always binary32. */
+typedef enum tg_precision {
+    TG_PREC_NATIVE = 0,   /* the operands' own type on the matrix cores      */
+    TG_PREC_BF16X3 = 1,   /* f32 operands split a = hi + mid (+ rest) into
+                             bf16 planes; 3 products hi.hi + hi.mid + mid.hi */
+    TG_PREC_BF16X6 = 2    /* 3-way split hi + mid + lo; 6 products hi.hi,
+                             hi.mid, mid.hi, hi.lo, lo.hi, mid.mid           */
+} tg_precision;
+
+/*
+ * Immutable input (a shared read-only tensor).  The descriptor names the
+ * stored matrix: `rows` x `cols` row-major with leading dimension `ld`.
+ * `trans` = 1 declares that the logical operand is the transpose of the
+ * stored matrix (B stored N x K, the weight layout of a decode product);
+ * only B may be transposed.
+ */
+typedef struct tg_in {
+    const void *data;     /* device pointer                                  */
+    int32_t dtype;        /* tg_dtype                                        */
+    int32_t trans;        /* 0 or 1                                          */
+    int64_t rows, cols, ld;
+} tg_in;
+
+/*
+ * Mutable output C (M x N row-major, leading dimension ld) together with its
+ * partition shape bm x bn: the output is split into ceil(M/bm) x ceil(N/bn)
+ * sub-tensors (edge sub-tensors clipped to the matrix) and each sub-tensor is
+ * owned by exactly one tile program.  bm = bn = 0 asks tile_gemm to choose
+ * the partition (the tile configuration picker); the chosen shape is
+ * written back into the descriptor.
+ */
+typedef struct tg_out {
+    void *data;           /* device pointer                                  */
+    int32_t dtype;        /* TG_F32 or TG_BF16 (round to nearest even)       */
+    int32_t reserved;
+    int64_t rows, cols, ld;
+    int32_t bm, bn;
+} tg_out;
+
+/*
+ * Kernel configuration.  bm x bn must equal the output partition; bk is the
+ * K-tile depth; wm x wn is the wavefront grid of one workgroup; `kind`
+ * selects the kernel family.  Unset fields (0) are filled by the picker.
+ */
+typedef enum tg_kind {
+    TG_KIND_AUTO = 0,
+    TG_KIND_TILED = 1,    /* LDS double-buffered MFMA tile program           */
+    TG_KIND_SKINNY = 2,   /* decode-shaped (M <= 16) streaming product       */
+    TG_KIND_SIMPLE = 3    /* small-tile kernel with no alignment demands     */
+} tg_kind;
+
+typedef struct tg_config {
+    int32_t kind;         /* tg_kind                                         */
+    int32_t bm, bn, bk;
+    int32_t wm, wn;
+    int32_t ksplit;       /* skinny kernel: wavefronts sharing one tile's K  */
+    int32_t reserved;
+} tg_config;
+
+typedef struct tg_opts {
+    int32_t precision;    /* tg_precision                                    */
+    int32_t checked;      /* 1: run tile_partition_check's rules before the
+                             launch (the default); 0: skip them (the
+                             unchecked twin used to measure their cost)      */
+    const float *scale_a; /* device, M floats or NULL (all ones): row scales */
+    const float *scale_b; /* device, N floats or NULL: output-column scales  */
+    const tg_config *config; /* host; NULL -> picker                         */
+    void *workspace;      /* device; needed by TG_PREC_BF16X3/X6             */
+    size_t workspace_bytes;
+    int32_t *write_count; /* device, M*N int32 (row-major, ld N) or NULL: each
+                             store adds 1 to its element's counter, so a
+                             correct launch leaves every counter at 1 more
+                             than the caller's initial value               */
+} tg_opts;
+
+/*
+ * tile_partition_check -- the host-side ownership rules of Sec. 3.4 and the
+ * data-race-freedom argument of App. A.
+ *
+ *   ins[0..n_in)   immutable inputs (host array of descriptors)
+ *   out            the mutable output with its partition bm x bn
+ *   n_prog, prog_offsets[n_prog+1], prog_tiles[...]  optional program map
+ *                  (host arrays): program p owns the sub-tensors with linear
+ *                  ids prog_tiles[prog_offsets[p] .. prog_offsets[p+1]), where
+ *                  sub-tensor (tm, tn) has id tm * ceil(N/bn) + tn.  With
+ *                  n_prog == 0 the one-program-per-sub-tensor grid is checked.
+ *
+ * Returns TG_E_ARG (NULL descriptor or data, bm/bn <= 0, negative sizes, a
+ * tile id off the grid), TG_E_SHAPE (ld < cols), TG_E_OVERLAP (a sub-tensor
+ * owned twice), TG_E_NOCOVER (a sub-tensor owned by nobody), TG_E_ALIAS (the
+ * output's byte range intersects an input's), else TG_OK.  Pure host code:
+ * no HIP call is made.
+ */
+tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
+                               const tg_out *out, int32_t n_prog,
+                               const int32_t *prog_offsets,
+                               const int32_t *prog_tiles);
+
+/*
+ * tile_gemm -- C = diag(scale_a) . A . B . diag(scale_b), one launch of tile
+ * programs over the partition of C (Sec. 3.6).
+ *
+ *   A  M x K (trans must be 0), B  K x N (or stored N x K with trans = 1),
+ *   C  M x N with partition bm x bn.
+ *   dtypes: A, B both TG_F32, both TG_BF16 or both TG_FP8_E4M3; or
+ *   A TG_BF16 with B TG_FP8_E4M3 (weight-only FP8: B is decoded exactly to
+ *   bf16 before the contraction).  C is TG_F32 or TG_BF16.
+ *   opts may be NULL (native precision, checked, picker).  Precision modes
+ *   BF16X3/X6 need f32 A and B and a workspace of
+ *   tile_gemm_workspace_size() bytes.
+ *   K == 0 stores zeros.  M == 0 or N == 0 enqueues nothing.
+ *
+ * Every output element is stored exactly once, by the program that owns its
+ * sub-tensor; nothing is read from C.
+ */
+tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
+                    const tg_opts *opts, tg_stream stream);
+
+/* Workspace bytes tile_gemm needs for these arguments (0 for native). */
+size_t tile_gemm_workspace_size(const tg_in *A, const tg_in *B,
+                                const tg_out *C, const tg_opts *opts);
+
+/*
+ * tile_gemm_plan -- the configuration and program map tile_gemm would use
+ * for these arguments, without launching.  cfg (host) receives the chosen
+ * configuration and *n_prog the number of tile programs.  When prog_offsets
+ * (n_prog+1 ints) and prog_tiles (ceil(M/bm)*ceil(N/bn) ints) are non-NULL
+ * they receive the program -> sub-tensor map, in the format
+ * tile_partition_check accepts.  Call once with NULL tables to size them.
+ */
+tg_status tile_gemm_plan(const tg_in *A, const tg_in *B, const tg_out *C,
+                         const tg_opts *opts, tg_config *cfg,
+                         int32_t *n_prog, int32_t *prog_offsets,
+                         int32_t *prog_tiles);
+
+/*
+ * Grouped GEMM: n independent problems C_i = A_i . B_i in ONE persistent
+ * launch whose programs walk the concatenated sub-tensor lists of all
+ * problems (the mapped-partition schedule applied across problems).
+ *
+ * tile_gemm_grouped_prepare validates every problem (each with the rules of
+ * tile_gemm, plus: no two outputs may share bytes, and no output may share
+ * bytes with any input of the launch), picks each problem's configuration and
+ * writes a problem table into the caller's device workspace with an
+ * asynchronous copy on `stream`.  Not capturable (it copies host memory).
+ * Supported: bf16 A and B, f32 or bf16 C, native precision.
+ * tile_gemm_grouped enqueues the single launch that reads that table; it
+ * allocates nothing and does not synchronise, so it may be captured into a
+ * HIP graph and replayed.  Pointers inside the table are those given to
+ * prepare; replays recompute the same outputs.
+ */
+size_t tile_gemm_grouped_workspace_size(int32_t n);
+tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
+                                    const tg_in *B, tg_out *C,
+                                    const tg_opts *opts, void *workspace,
+                                    size_t workspace_bytes, tg_stream stream);
+tg_status tile_gemm_grouped(void *workspace, tg_stream stream);
+
+/*
+ * tile_error_norm -- binary64 reductions for the relative Frobenius error of
+ * a result against a binary64 reference, on the GPU:
+ *   out[0] = sum (C[i] - R[i])^2,  out[1] = sum R[i]^2   over i < n
+ * C: device, n elements of c_dtype (TG_F32 or TG_BF16), read as a dense
+ * array (pass matrices with ld == cols); R: device, n binary64 values.
+ * out: device, TG_ERROR_NORM_DOUBLES doubles, all overwritten (entries past
+ * the first two hold per-workgroup partial sums).  The summation order is
+ * fixed, so repeated calls give identical results.
+ */
+#define TG_ERROR_NORM_DOUBLES 514
+tg_status tile_error_norm(const void *C, int32_t c_dtype, const double *R,
+                          int64_t n, double *out, tg_stream stream);
+
+const char *tg_status_str(int32_t status);
+const char *tg_last_error(void);
+
+/* Number of compute units of the current device (0 if unknown). */
+int32_t tg_device_cus(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILEGEMM_H */

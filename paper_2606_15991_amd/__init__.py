@@ -1,0 +1,329 @@
+"""Python binding of libtilegemm.so (the C ABI declared in include/tilegemm.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the shared library.  torch supplies device memory and streams.
+The functions carry the names of the C entry points:
+
+  tile_gemm(A, B, C, ...)            C = A . B into a partitioned output
+  tile_gemm_plan(A, B, C, ...)       configuration + program -> sub-tensor map
+  tile_partition_check(ins, out, ...)  ownership rules (host only)
+  tile_gemm_grouped_prepare / tile_gemm_grouped   one launch, many problems
+  tile_error_norm(C, R, out)         binary64 error reductions on the GPU
+
+Following the prepare/recover protocol of the paper (Sec. 3.3), tile_gemm
+returns the very tensor objects it was given.  The library is required: if
+libtilegemm.so is missing the import of this package fails.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtilegemm.so")
+
+# tg_status
+TG_OK, TG_E_ARG, TG_E_DTYPE, TG_E_SHAPE, TG_E_OVERLAP, TG_E_NOCOVER, \
+    TG_E_ALIAS, TG_E_WORKSPACE, TG_E_UNSUPPORTED, TG_E_HIP = range(10)
+# tg_dtype
+TG_F32, TG_BF16, TG_FP8_E4M3 = 0, 1, 2
+# tg_precision
+TG_PREC_NATIVE, TG_PREC_BF16X3, TG_PREC_BF16X6 = 0, 1, 2
+# tg_kind
+TG_KIND_AUTO, TG_KIND_TILED, TG_KIND_SKINNY, TG_KIND_SIMPLE = 0, 1, 2, 3
+TG_ERROR_NORM_DOUBLES = 514
+
+PRECISIONS = {"native": TG_PREC_NATIVE, "bf16x3": TG_PREC_BF16X3,
+              "bf16x6": TG_PREC_BF16X6}
+KINDS = {"auto": TG_KIND_AUTO, "tiled": TG_KIND_TILED,
+         "skinny": TG_KIND_SKINNY, "simple": TG_KIND_SIMPLE}
+
+
+class tg_in(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("trans", ctypes.c_int32), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("ld", ctypes.c_int64)]
+
+
+class tg_out(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("bm", ctypes.c_int32), ("bn", ctypes.c_int32)]
+
+
+class tg_config(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("bm", ctypes.c_int32),
+                ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
+                ("wm", ctypes.c_int32), ("wn", ctypes.c_int32),
+                ("ksplit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_
+                if f != "reserved"}
+
+
+class tg_opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("checked", ctypes.c_int32),
+                ("scale_a", ctypes.c_void_p), ("scale_b", ctypes.c_void_p),
+                ("config", ctypes.POINTER(tg_config)),
+                ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t),
+                ("write_count", ctypes.c_void_p)]
+
+
+class TileGemmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{status_str(status)}: {message}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with "
+            "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    i32 = ctypes.c_int32
+    lib.tile_partition_check.argtypes = [P(tg_in), i32, P(tg_out), i32,
+                                         ctypes.c_void_p, ctypes.c_void_p]
+    lib.tile_gemm.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
+                              ctypes.c_void_p]
+    lib.tile_gemm_workspace_size.argtypes = [P(tg_in), P(tg_in), P(tg_out),
+                                             P(tg_opts)]
+    lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
+    lib.tile_gemm_plan.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
+                                   P(tg_config), P(i32), ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    lib.tile_gemm_grouped_workspace_size.argtypes = [i32]
+    lib.tile_gemm_grouped_workspace_size.restype = ctypes.c_size_t
+    lib.tile_gemm_grouped_prepare.argtypes = [i32, P(tg_in), P(tg_in),
+                                              P(tg_out), P(tg_opts),
+                                              ctypes.c_void_p, ctypes.c_size_t,
+                                              ctypes.c_void_p]
+    lib.tile_gemm_grouped.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.tile_error_norm.argtypes = [ctypes.c_void_p, i32, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    lib.tg_status_str.argtypes = [i32]
+    lib.tg_status_str.restype = ctypes.c_char_p
+    lib.tg_last_error.argtypes = []
+    lib.tg_last_error.restype = ctypes.c_char_p
+    lib.tg_device_cus.argtypes = []
+    lib.tg_device_cus.restype = i32
+    for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
+              "tile_gemm_grouped_prepare", "tile_gemm_grouped",
+              "tile_error_norm"):
+        getattr(lib, f).restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def status_str(st) -> str:
+    return lib.tg_status_str(int(st)).decode()
+
+
+def last_error() -> str:
+    return lib.tg_last_error().decode()
+
+
+def _raise(st):
+    if st != TG_OK:
+        raise TileGemmError(st, last_error())
+
+
+_DT = {torch.float32: TG_F32, torch.bfloat16: TG_BF16,
+       torch.float8_e4m3fn: TG_FP8_E4M3}
+
+
+def dtype_code(t: torch.dtype) -> int:
+    try:
+        return _DT[t]
+    except KeyError:
+        raise TileGemmError(TG_E_DTYPE, f"unsupported dtype {t}") from None
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2:
+        raise TileGemmError(TG_E_SHAPE, "operands are 2-D matrices")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise TileGemmError(TG_E_SHAPE, "rows must be contiguous")
+    return int(t.stride(0)) if t.shape[0] > 1 else int(max(t.shape[1], 1))
+
+
+def make_in(t: torch.Tensor, trans: bool = False) -> tg_in:
+    """Immutable-input descriptor of a 2-D row-major tensor (stored shape)."""
+    return tg_in(t.data_ptr(), dtype_code(t.dtype), int(trans),
+                 int(t.shape[0]), int(t.shape[1]), _ld(t))
+
+
+def make_out(t: torch.Tensor, bm: int = 0, bn: int = 0) -> tg_out:
+    """Mutable-output descriptor with its partition bm x bn."""
+    return tg_out(t.data_ptr(), dtype_code(t.dtype), 0, int(t.shape[0]),
+                  int(t.shape[1]), _ld(t), int(bm), int(bn))
+
+
+def make_config(cfg) -> tg_config:
+    if cfg is None:
+        return None
+    if isinstance(cfg, tg_config):
+        return cfg
+    c = tg_config()
+    for k, v in cfg.items():
+        if k == "kind" and isinstance(v, str):
+            v = KINDS[v]
+        setattr(c, k, int(v))
+    return c
+
+
+def _stream(stream):
+    if stream is None:
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+        return None
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def make_opts(precision="native", scale_a=None, scale_b=None, config=None,
+              workspace=None, write_count=None, checked=True):
+    o = tg_opts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) \
+        else int(precision)
+    o.checked = int(bool(checked))
+    o.scale_a = _ptr(scale_a)
+    o.scale_b = _ptr(scale_b)
+    c = make_config(config)
+    o._cfg = c  # keep alive
+    o.config = ctypes.pointer(c) if c is not None else None
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.write_count = _ptr(write_count)
+    return o
+
+
+def tile_gemm(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
+              scale_a=None, scale_b=None, config=None, workspace=None,
+              write_count=None, checked=True, stream=None):
+    """C = diag(scale_a) A B diag(scale_b) into C's bm x bn partition.
+
+    B is K x N, or the stored N x K matrix when b_trans.  BF16x3/x6 need a
+    workspace (allocated here from torch when not given).  Returns
+    (A, B, C) -- the same tensor objects."""
+    da, db = make_in(A), make_in(B, b_trans)
+    dc = make_out(C, bm, bn)
+    o = make_opts(precision, scale_a, scale_b, config, workspace, write_count,
+                  checked)
+    if o.precision != TG_PREC_NATIVE and workspace is None:
+        need = lib.tile_gemm_workspace_size(da, db, dc, o)
+        if need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
+            o.workspace = workspace.data_ptr()
+            o.workspace_bytes = need
+    _raise(lib.tile_gemm(da, db, dc, o, _stream(stream)))
+    tile_gemm.last_partition = (dc.bm, dc.bn)
+    return A, B, C
+
+
+def tile_gemm_workspace_size(A, B, C, bm=0, bn=0, *, b_trans=False,
+                             precision="native") -> int:
+    return int(lib.tile_gemm_workspace_size(
+        make_in(A), make_in(B, b_trans), make_out(C, bm, bn),
+        make_opts(precision)))
+
+
+def tile_gemm_plan(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
+                   config=None, want_map=True):
+    """(config dict, n_prog, prog_offsets list, prog_tiles list)."""
+    da, db = make_in(A), make_in(B, b_trans)
+    dc = make_out(C, bm, bn)
+    o = make_opts(precision, config=config)
+    cfg = tg_config()
+    n = ctypes.c_int32(0)
+    _raise(lib.tile_gemm_plan(da, db, dc, o, cfg, ctypes.byref(n), None,
+                              None))
+    if not want_map:
+        return cfg.as_dict(), n.value, None, None
+    tm = -(-int(C.shape[0]) // cfg.bm) if C.shape[0] else 0
+    tn = -(-int(C.shape[1]) // cfg.bn) if C.shape[1] else 0
+    offs = (ctypes.c_int32 * (n.value + 1))()
+    ids = (ctypes.c_int32 * max(tm * tn, 1))()
+    _raise(lib.tile_gemm_plan(da, db, dc, o, cfg, ctypes.byref(n), offs,
+                              ids))
+    return cfg.as_dict(), n.value, list(offs), list(ids)[:tm * tn]
+
+
+def tile_partition_check(ins, out, prog_offsets=None, prog_tiles=None) -> int:
+    """Status of the ownership rules for descriptors `ins` (list of tg_in)
+    and `out` (tg_out with its partition).  Host only; returns the status."""
+    arr = (tg_in * max(len(ins), 1))(*ins)
+    if prog_offsets is None:
+        return int(lib.tile_partition_check(arr, len(ins), out, 0, None,
+                                            None))
+    po = (ctypes.c_int32 * len(prog_offsets))(*prog_offsets)
+    pt = (ctypes.c_int32 * max(len(prog_tiles), 1))(*prog_tiles)
+    return int(lib.tile_partition_check(arr, len(ins), out,
+                                        len(prog_offsets) - 1, po, pt))
+
+
+def tile_gemm_grouped_workspace_size(n: int) -> int:
+    return int(lib.tile_gemm_grouped_workspace_size(int(n)))
+
+
+class GroupedLaunch:
+    """A prepared grouped launch: the device workspace holding its problem
+    table plus the tensors it borrows (kept alive while the launch exists)."""
+
+    def __init__(self, As, Bs, Cs, workspace, partitions):
+        self.As, self.Bs, self.Cs = As, Bs, Cs
+        self.workspace = workspace
+        self.partitions = partitions
+
+
+def tile_gemm_grouped_prepare(As, Bs, Cs, *, b_trans=False, config=None,
+                              workspace=None, stream=None) -> GroupedLaunch:
+    n = len(As)
+    ia = (tg_in * n)(*[make_in(a) for a in As])
+    ib = (tg_in * n)(*[make_in(b, b_trans) for b in Bs])
+    oc = (tg_out * n)(*[make_out(c) for c in Cs])
+    need = tile_gemm_grouped_workspace_size(n)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=Cs[0].device)
+    o = make_opts(config=config)
+    _raise(lib.tile_gemm_grouped_prepare(
+        n, ia, ib, oc, o, workspace.data_ptr(),
+        workspace.numel() * workspace.element_size(), _stream(stream)))
+    return GroupedLaunch(As, Bs, Cs, workspace,
+                         [(oc[i].bm, oc[i].bn) for i in range(n)])
+
+
+def tile_gemm_grouped(launch: GroupedLaunch, stream=None):
+    _raise(lib.tile_gemm_grouped(launch.workspace.data_ptr(),
+                                 _stream(stream)))
+    return launch.Cs
+
+
+def tile_error_norm(C, R, out=None, stream=None):
+    """(sum (C-R)^2, sum R^2) in binary64 on the GPU; returns the device
+    buffer of TG_ERROR_NORM_DOUBLES doubles (first two entries)."""
+    if out is None:
+        out = torch.empty(TG_ERROR_NORM_DOUBLES, dtype=torch.float64,
+                          device=C.device)
+    assert R.dtype == torch.float64 and R.numel() == C.numel()
+    _raise(lib.tile_error_norm(C.data_ptr(), dtype_code(C.dtype),
+                               R.data_ptr(), C.numel(), out.data_ptr(),
+                               _stream(stream)))
+    return out
+
+
+def device_cus() -> int:
+    return int(lib.tg_device_cus())

@@ -1,0 +1,147 @@
+// gemm_skinny.hip -- decode-shaped products y[M x N] = x[M x K] . W^T with
+// M <= 16 and W stored N x K (bf16, or OCP E4M3 with one fp32 scale per row
+// of W, i.e. per output column).
+//
+// The work is bound by streaming W from HBM once (arithmetic intensity about
+// M flop per weight byte).  One tile program owns the 16 output columns
+// n0 .. n0+15 for all M rows; its KS wavefronts split K between them and
+// stream their share of the 16 weight rows with 16-byte loads, several in
+// flight per lane.  The contraction runs on the 16x16x32 bf16 matrix
+// instruction with the weight rows as the A operand and the (zero-padded)
+// activation rows as the B operand; E4M3 weights are decoded exactly to
+// bf16 in registers first (there is no mixed bf16 x e4m3 matrix
+// instruction).  The KS partial tiles are summed in LDS in a fixed order,
+// and one wavefront stores the sub-tensor: deterministic, no atomics, no
+// workspace.
+#include "tg_device.hpp"
+#include "tg_internal.hpp"
+
+namespace tg {
+namespace {
+
+constexpr int UNROLL = 4;
+
+template <int WDT, int KS, bool CBF16>
+__global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
+    // Elements of K covered by one 16-byte weight load per lane group:
+    // bf16: 8 per lane, 4 lane groups -> 32;  e4m3: 16 per lane -> 64.
+    constexpr int EPL = WDT == TG_BF16 ? 8 : 16;
+    constexpr int KSTEP = 4 * EPL;
+    __shared__ f32x4 part[KS][64];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n0 = blockIdx.x * 16;
+    const int r = lane & 15, grp = lane >> 4;
+    int wrow = n0 + r;
+    wrow = wrow < g.N ? wrow : g.N - 1;
+    const bool xrow_ok = r < g.M;
+    const int xrow = xrow_ok ? r : 0;
+
+    const char *W = static_cast<const char *>(g.w) +
+                    (int64_t)wrow * g.ldw * (WDT == TG_BF16 ? 2 : 1);
+    const uint16_t *X = static_cast<const uint16_t *>(g.x) +
+                        (int64_t)xrow * g.ldx;
+
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const int nsteps = (g.K + KSTEP - 1) / KSTEP;
+    // wave w takes super-steps w, w + KS, ... of UNROLL K steps each
+    for (int s0 = wave * UNROLL; s0 < nsteps; s0 += KS * UNROLL) {
+        uint4 wv[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            int k = (s0 + u) * KSTEP + grp * EPL;
+            if (s0 + u < nsteps && k < g.K)
+                wv[u] = ld16(W + (int64_t)k * (WDT == TG_BF16 ? 2 : 1));
+            else
+                wv[u] = uint4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            int k = (s0 + u) * KSTEP + grp * EPL;
+            bool ok = xrow_ok && s0 + u < nsteps && k < g.K;
+            if constexpr (WDT == TG_BF16) {
+                uint4 xv = ok ? ld16(X + k) : uint4{0, 0, 0, 0};
+                acc = mfma16_bf16(__builtin_bit_cast(i32x4, wv[u]),
+                                  __builtin_bit_cast(i32x4, xv), acc);
+            } else {
+                uint4 x0 = ok ? ld16(X + k) : uint4{0, 0, 0, 0};
+                uint4 x1 = ok ? ld16(X + k + 8) : uint4{0, 0, 0, 0};
+                uint2 w01 = e4m3x4_to_bf16x4(wv[u].x);
+                uint2 w23 = e4m3x4_to_bf16x4(wv[u].y);
+                uint2 w45 = e4m3x4_to_bf16x4(wv[u].z);
+                uint2 w67 = e4m3x4_to_bf16x4(wv[u].w);
+                i32x4 wa = {(int)w01.x, (int)w01.y, (int)w23.x, (int)w23.y};
+                i32x4 wb = {(int)w45.x, (int)w45.y, (int)w67.x, (int)w67.y};
+                acc = mfma16_bf16(wa, __builtin_bit_cast(i32x4, x0), acc);
+                acc = mfma16_bf16(wb, __builtin_bit_cast(i32x4, x1), acc);
+            }
+        }
+    }
+
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    f32x4 s = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < KS; ++w) {
+        f32x4 p = part[w][lane];
+        s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] += p[3];
+    }
+    // 16 x 16 result layout: lane l, register v holds row 4 * (l / 16) + v
+    // (a weight row, i.e. output column) and column l % 16 (an output row).
+    const int m = lane & 15;
+    if (m >= g.M) return;
+    const float sa = g.scale_a ? g.scale_a[m] : 1.0f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int n = n0 + 4 * grp + v;
+        if (n < g.N) {
+            float y = s[v] * sa;
+            if (g.scale_w) y *= g.scale_w[n];
+            int64_t off = (int64_t)m * g.ldy + n;
+            if constexpr (CBF16)
+                static_cast<uint16_t *>(g.y)[off] = f32_to_bf16_bits(y);
+            else
+                static_cast<float *>(g.y)[off] = y;
+            if (g.wcount) atomicAdd(&g.wcount[(int64_t)m * g.N + n], 1);
+        }
+    }
+}
+
+template <int WDT, int KS>
+hipError_t launch_ks(int c_bf16, const SkinnyArgs &a, hipStream_t st) {
+    dim3 grid((a.N + 15) / 16), block(KS * 64);
+    if (c_bf16)
+        hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, true>), grid, block,
+                           0, st, a);
+    else
+        hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, false>), grid, block,
+                           0, st, a);
+    return hipGetLastError();
+}
+
+template <int WDT>
+hipError_t launch_w(int c_bf16, int ksplit, const SkinnyArgs &a,
+                    hipStream_t st) {
+    switch (ksplit) {
+    case 1: return launch_ks<WDT, 1>(c_bf16, a, st);
+    case 2: return launch_ks<WDT, 2>(c_bf16, a, st);
+    case 4: return launch_ks<WDT, 4>(c_bf16, a, st);
+    case 8: return launch_ks<WDT, 8>(c_bf16, a, st);
+    case 16: return launch_ks<WDT, 16>(c_bf16, a, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_skinny(int w_dtype, int c_bf16, int bn, int ksplit,
+                         const SkinnyArgs &a, hipStream_t st) {
+    if (bn != 16) return hipErrorInvalidValue;
+    if (w_dtype == TG_BF16) return launch_w<TG_BF16>(c_bf16, ksplit, a, st);
+    if (w_dtype == TG_FP8_E4M3)
+        return launch_w<TG_FP8_E4M3>(c_bf16, ksplit, a, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tg

@@ -1,0 +1,766 @@
+// tilegemm.cpp -- host side of the C ABI: argument validation, the
+// ownership checks of tile_partition_check, configuration choice, the
+// program map, and kernel dispatch.  No call here allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "tg_internal.hpp"
+
+using namespace tg;
+
+namespace {
+
+thread_local std::string g_err;
+
+tg_status fail(tg_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+tg_status hip_fail(hipError_t e, const char *what) {
+    return fail(TG_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int esize(int dt) {
+    switch (dt) {
+    case TG_F32: return 4;
+    case TG_BF16: return 2;
+    case TG_FP8_E4M3: return 1;
+    default: return 0;
+    }
+}
+
+struct Range {
+    uintptr_t lo, hi;  // [lo, hi); empty when lo == hi
+};
+
+Range byte_range(const void *data, int64_t rows, int64_t cols, int64_t ld,
+                 int es) {
+    Range r{(uintptr_t)data, (uintptr_t)data};
+    if (rows > 0 && cols > 0)
+        r.hi = r.lo + (uintptr_t)(((rows - 1) * ld + cols) * es);
+    return r;
+}
+
+bool intersect(const Range &a, const Range &b) {
+    if (a.lo == a.hi || b.lo == b.hi) return false;
+    return a.lo < b.hi && b.lo < a.hi;
+}
+
+tg_status check_in(const tg_in *d, const char *name) {
+    if (!d) return fail(TG_E_ARG, "%s: NULL descriptor", name);
+    if (esize(d->dtype) == 0)
+        return fail(TG_E_ARG, "%s: unknown dtype %d", name, d->dtype);
+    if (d->rows < 0 || d->cols < 0)
+        return fail(TG_E_ARG, "%s: negative size", name);
+    if (d->trans != 0 && d->trans != 1)
+        return fail(TG_E_ARG, "%s: trans must be 0 or 1", name);
+    if (d->rows > 0 && d->cols > 0 && !d->data)
+        return fail(TG_E_ARG, "%s: NULL data", name);
+    if (d->rows > 1 && d->ld < d->cols)
+        return fail(TG_E_SHAPE, "%s: ld %lld < cols %lld", name,
+                    (long long)d->ld, (long long)d->cols);
+    if (d->ld < 0) return fail(TG_E_SHAPE, "%s: negative ld", name);
+    return TG_OK;
+}
+
+tg_status check_out(const tg_out *d, bool need_partition) {
+    if (!d) return fail(TG_E_ARG, "C: NULL descriptor");
+    if (d->dtype != TG_F32 && d->dtype != TG_BF16)
+        return fail(TG_E_ARG, "C: dtype must be TG_F32 or TG_BF16");
+    if (d->rows < 0 || d->cols < 0) return fail(TG_E_ARG, "C: negative size");
+    if (d->rows > 0 && d->cols > 0 && !d->data)
+        return fail(TG_E_ARG, "C: NULL data");
+    if (need_partition && (d->bm <= 0 || d->bn <= 0))
+        return fail(TG_E_ARG, "C: partition %d x %d must be positive", d->bm,
+                    d->bn);
+    if (d->bm < 0 || d->bn < 0) return fail(TG_E_ARG, "C: negative partition");
+    if (d->rows > 1 && d->ld < d->cols)
+        return fail(TG_E_SHAPE, "C: ld %lld < cols %lld", (long long)d->ld,
+                    (long long)d->cols);
+    if (d->ld < 0) return fail(TG_E_SHAPE, "C: negative ld");
+    return TG_OK;
+}
+
+// Program-map rules: every id on the grid, no sub-tensor twice, none missed.
+tg_status check_map(int64_t tiles, int32_t n_prog, const int32_t *offs,
+                    const int32_t *ids) {
+    if (n_prog < 0) return fail(TG_E_ARG, "negative program count");
+    if (n_prog == 0) return TG_OK;
+    if (!offs || !ids) return fail(TG_E_ARG, "NULL program map");
+    if (offs[0] != 0) return fail(TG_E_ARG, "program map must start at 0");
+    std::vector<uint8_t> seen((size_t)tiles, 0);
+    for (int32_t p = 0; p < n_prog; ++p) {
+        if (offs[p + 1] < offs[p])
+            return fail(TG_E_ARG, "program %d: decreasing offsets", p);
+        for (int32_t q = offs[p]; q < offs[p + 1]; ++q) {
+            int64_t t = ids[q];
+            if (t < 0 || t >= tiles)
+                return fail(TG_E_ARG, "program %d: sub-tensor %lld off the grid",
+                            p, (long long)t);
+            if (seen[(size_t)t])
+                return fail(TG_E_OVERLAP,
+                            "sub-tensor %lld owned by two programs (second: %d)",
+                            (long long)t, p);
+            seen[(size_t)t] = 1;
+        }
+    }
+    for (int64_t t = 0; t < tiles; ++t)
+        if (!seen[(size_t)t])
+            return fail(TG_E_NOCOVER, "sub-tensor %lld owned by no program",
+                        (long long)t);
+    return TG_OK;
+}
+
+tg_status check_alias(const tg_in *ins, int32_t n_in, const tg_out *out) {
+    Range ro = byte_range(out->data, out->rows, out->cols, out->ld,
+                          esize(out->dtype));
+    for (int32_t i = 0; i < n_in; ++i) {
+        Range ri = byte_range(ins[i].data, ins[i].rows, ins[i].cols, ins[i].ld,
+                              esize(ins[i].dtype));
+        if (intersect(ro, ri))
+            return fail(TG_E_ALIAS, "output shares bytes with input %d", i);
+    }
+    return TG_OK;
+}
+
+// ------------------------------------------------------------- device info
+
+int device_cus() {
+    static std::mutex mu;
+    static std::unordered_map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                              dev) != hipSuccess)
+        cus = 0;
+    cache[dev] = cus;
+    return cus;
+}
+
+// --------------------------------------------------------------- problem
+
+struct Problem {
+    int64_t M, N, K;
+    int a_dt, b_dt;
+    bool b_nk;
+    bool c_bf16;
+    int precision;
+};
+
+tg_status describe(const tg_in *A, const tg_in *B, const tg_out *C,
+                   const tg_opts *o, Problem &p) {
+    tg_status st;
+    if ((st = check_in(A, "A")) != TG_OK) return st;
+    if ((st = check_in(B, "B")) != TG_OK) return st;
+    if ((st = check_out(C, false)) != TG_OK) return st;
+    if (A->trans) return fail(TG_E_UNSUPPORTED, "A must not be transposed");
+    p.M = A->rows;
+    p.K = A->cols;
+    p.b_nk = B->trans == 1;
+    int64_t bk = p.b_nk ? B->cols : B->rows;
+    p.N = p.b_nk ? B->rows : B->cols;
+    if (bk != p.K)
+        return fail(TG_E_SHAPE, "A is %lld x %lld but B has K = %lld",
+                    (long long)A->rows, (long long)A->cols, (long long)bk);
+    if (C->rows != p.M || C->cols != p.N)
+        return fail(TG_E_SHAPE, "C is %lld x %lld, expected %lld x %lld",
+                    (long long)C->rows, (long long)C->cols, (long long)p.M,
+                    (long long)p.N);
+    if (p.M > INT32_MAX || p.N > INT32_MAX || p.K > INT32_MAX)
+        return fail(TG_E_SHAPE, "dimension exceeds 2^31 - 1");
+    p.a_dt = A->dtype;
+    p.b_dt = B->dtype;
+    p.c_bf16 = C->dtype == TG_BF16;
+    p.precision = o ? o->precision : TG_PREC_NATIVE;
+    if (p.precision < TG_PREC_NATIVE || p.precision > TG_PREC_BF16X6)
+        return fail(TG_E_ARG, "unknown precision %d", p.precision);
+    bool same = p.a_dt == p.b_dt;
+    bool w8 = p.a_dt == TG_BF16 && p.b_dt == TG_FP8_E4M3;
+    if (!same && !w8)
+        return fail(TG_E_DTYPE, "dtype pair (%d, %d) not provided", p.a_dt,
+                    p.b_dt);
+    if (p.precision != TG_PREC_NATIVE &&
+        (p.a_dt != TG_F32 || p.b_dt != TG_F32))
+        return fail(TG_E_DTYPE, "split precision needs f32 A and B");
+    return TG_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Can the tiled kernel take this operand layout?
+bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B, int dt) {
+    int es = esize(dt);
+    int epc = 16 / es;
+    if (p.a_dt != p.b_dt) return false;
+    if (dt == TG_FP8_E4M3 && !p.b_nk) return false;
+    if (!aligned16(A->data) || !aligned16(B->data)) return false;
+    if ((A->ld * es) % 16 || (B->ld * es) % 16) return false;
+    if (p.K % epc) return false;
+    if (!p.b_nk && (p.N % epc)) return false;
+    return true;
+}
+
+bool skinny_ok(const Problem &p, const tg_in *A, const tg_in *B) {
+    if (p.M > 16 || !p.b_nk || p.a_dt != TG_BF16) return false;
+    if (p.b_dt != TG_BF16 && p.b_dt != TG_FP8_E4M3) return false;
+    int epl = p.b_dt == TG_BF16 ? 8 : 16;
+    if (p.K % epl) return false;
+    if (!aligned16(A->data) || !aligned16(B->data)) return false;
+    if ((A->ld * 2) % 16 || (B->ld * esize(p.b_dt)) % 16) return false;
+    return true;
+}
+
+int find_variant(int dt, int bm, int bn, int wm, int wn, bool b_nk,
+                 bool c_bf16) {
+    int n = tiled_variant_count();
+    for (int i = 0; i < n; ++i) {
+        const TiledVariant &v = tiled_variant(i);
+        if (v.dtype == dt && v.bm == bm && v.bn == bn && v.b_nk == b_nk &&
+            v.c_bf16 == c_bf16 && (wm == 0 || v.wm == wm) &&
+            (wn == 0 || v.wn == wn))
+            return i;
+    }
+    return -1;
+}
+
+// Default tile choice: the largest square tile that still gives every
+// compute unit close to one sub-tensor.
+int default_tile(int dt, int64_t M, int64_t N, int cus) {
+    const int sizes_lp[] = {256, 128, 64, 32};
+    const int sizes_f32[] = {128, 64, 32};
+    const int *sz = dt == TG_F32 ? sizes_f32 : sizes_lp;
+    int nsz = dt == TG_F32 ? 3 : 4;
+    if (cus <= 0) cus = 256;
+    for (int i = 0; i < nsz; ++i) {
+        int64_t t = ((M + sz[i] - 1) / sz[i]) * ((N + sz[i] - 1) / sz[i]);
+        if (t * 4 >= (int64_t)cus * 3) return sz[i];
+    }
+    return sz[nsz - 1];
+}
+
+struct Launch {
+    tg_config cfg;
+    int variant;       // tiled kernel index, or -1
+    int gemm_dt;       // dtype the contraction reads (bf16 for split modes)
+    int64_t Kc;        // contraction length seen by the kernel
+    Sched s;
+};
+
+tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
+                 const tg_out *C, const tg_opts *o, Launch &L) {
+    const tg_config *uc = o ? o->config : nullptr;
+    tg_config cfg{};
+    if (uc) cfg = *uc;
+    if (cfg.kind < TG_KIND_AUTO || cfg.kind > TG_KIND_SIMPLE)
+        return fail(TG_E_ARG, "unknown kernel kind %d", cfg.kind);
+    int np = p.precision == TG_PREC_BF16X3 ? 3
+             : p.precision == TG_PREC_BF16X6 ? 6 : 1;
+    L.gemm_dt = np > 1 ? TG_BF16 : p.a_dt;
+    L.Kc = p.K * np;
+    // the partition of C, when given, fixes the sub-tensor shape
+    if (C->bm > 0 || C->bn > 0) {
+        if (C->bm <= 0 || C->bn <= 0)
+            return fail(TG_E_ARG, "C partition %d x %d: both must be set",
+                        C->bm, C->bn);
+        if (cfg.bm && cfg.bm != C->bm)
+            return fail(TG_E_ARG, "config bm %d != partition bm %d", cfg.bm,
+                        C->bm);
+        if (cfg.bn && cfg.bn != C->bn)
+            return fail(TG_E_ARG, "config bn %d != partition bn %d", cfg.bn,
+                        C->bn);
+        cfg.bm = C->bm;
+        cfg.bn = C->bn;
+    }
+    // split precisions run the tiled bf16 kernel on the plane operands,
+    // whose layout the library lays out itself (always aligned)
+    bool t_ok = np > 1 ? ((p.K * np) % 8 == 0 && (p.b_nk || p.N % 8 == 0))
+                       : tiled_ok(p, A, B, p.a_dt);
+    bool s_ok = np == 1 && skinny_ok(p, A, B);
+    if (cfg.kind == TG_KIND_AUTO) {
+        if (s_ok && (cfg.bm == 0 || (cfg.bm >= p.M && cfg.bm <= 16)) &&
+            (cfg.bn == 0 || cfg.bn == 16))
+            cfg.kind = TG_KIND_SKINNY;
+        else if (t_ok && (cfg.bm == 0 ||
+                          find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm,
+                                       cfg.wn, p.b_nk, p.c_bf16) >= 0))
+            cfg.kind = TG_KIND_TILED;
+        else
+            cfg.kind = TG_KIND_SIMPLE;
+    }
+    int cus = device_cus();
+    L.variant = -1;
+    if (cfg.kind == TG_KIND_SKINNY) {
+        if (!s_ok)
+            return fail(TG_E_UNSUPPORTED,
+                        "decode kernel needs M <= 16, bf16 A, bf16/e4m3 B "
+                        "stored N x K, aligned 16-byte rows");
+        if (cfg.bm == 0) cfg.bm = 16;
+        if (cfg.bn == 0) cfg.bn = 16;
+        if (cfg.bm < p.M || cfg.bm > 16 || cfg.bn != 16)
+            return fail(TG_E_UNSUPPORTED,
+                        "decode kernel owns %d-row x 16-column sub-tensors "
+                        "(partition %d x %d)", 16, cfg.bm, cfg.bn);
+        cfg.bm = 16;
+        if (cfg.ksplit == 0) {
+            // enough wavefronts to keep every compute unit streaming
+            int64_t progs = (p.N + 15) / 16;
+            int ks = 1;
+            while (ks < 16 && progs * ks < (int64_t)std::max(cus, 1) * 16)
+                ks *= 2;
+            cfg.ksplit = ks;
+        }
+        if (cfg.ksplit != 1 && cfg.ksplit != 2 && cfg.ksplit != 4 &&
+            cfg.ksplit != 8 && cfg.ksplit != 16)
+            return fail(TG_E_UNSUPPORTED, "ksplit %d not in {1,2,4,8,16}",
+                        cfg.ksplit);
+        cfg.bk = p.b_dt == TG_BF16 ? 32 : 64;
+        cfg.wm = 1;
+        cfg.wn = 1;
+        L.s.tiles_m = 1;
+        L.s.tiles_n = (int32_t)((p.N + 15) / 16);
+        L.s.n_tiles = L.s.tiles_n;
+        L.s.n_prog = L.s.n_tiles;
+        L.s.group_m = 1;
+    } else if (cfg.kind == TG_KIND_TILED) {
+        if (!t_ok)
+            return fail(TG_E_UNSUPPORTED,
+                        "tiled kernel needs matching A/B dtypes, 16-byte "
+                        "aligned rows, K (and N for B stored K x N) a "
+                        "multiple of 16 bytes, e4m3 B stored N x K");
+        if (cfg.bm == 0 && cfg.bn == 0) {
+            int t = default_tile(L.gemm_dt, p.M, p.N, cus);
+            cfg.bm = cfg.bn = t;
+        } else if (cfg.bm == 0 || cfg.bn == 0) {
+            return fail(TG_E_ARG, "config bm/bn: set both or neither");
+        }
+        L.variant = find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
+                                 p.b_nk, p.c_bf16);
+        if (L.variant < 0)
+            return fail(TG_E_UNSUPPORTED,
+                        "no tiled kernel for dtype %d, %d x %d, waves %d x %d",
+                        L.gemm_dt, cfg.bm, cfg.bn, cfg.wm, cfg.wn);
+        const TiledVariant &v = tiled_variant(L.variant);
+        cfg.bk = v.bk;
+        cfg.wm = v.wm;
+        cfg.wn = v.wn;
+        cfg.ksplit = 1;
+        L.s.tiles_m = (int32_t)((p.M + cfg.bm - 1) / cfg.bm);
+        L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
+        L.s.n_tiles = L.s.tiles_m * L.s.tiles_n;
+        int occ = cus > 0 ? tiled_occupancy(L.variant) : 1;
+        int64_t cap = (int64_t)(cus > 0 ? cus : 256) * occ;
+        L.s.n_prog = (int32_t)std::min<int64_t>(L.s.n_tiles, cap);
+        L.s.group_m = 8;
+    } else {  // simple
+        if (np > 1)
+            return fail(TG_E_UNSUPPORTED,
+                        "split precision runs on the tiled kernel only");
+        if (cfg.bm == 0 && cfg.bn == 0) cfg.bm = cfg.bn = 64;
+        if (cfg.bm <= 0 || cfg.bn <= 0 || cfg.bm > 64 || cfg.bn > 64)
+            return fail(TG_E_UNSUPPORTED,
+                        "simple kernel partitions are at most 64 x 64");
+        cfg.bk = 32;
+        cfg.wm = 4;
+        cfg.wn = 1;
+        cfg.ksplit = 1;
+        L.s.tiles_m = (int32_t)((p.M + cfg.bm - 1) / cfg.bm);
+        L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
+        L.s.n_tiles = L.s.tiles_m * L.s.tiles_n;
+        L.s.n_prog = L.s.n_tiles;
+        L.s.group_m = 1;
+    }
+    L.cfg = cfg;
+    return TG_OK;
+}
+
+// Program p -> owned sub-tensor ids, as the kernels walk them.
+void build_map(const Launch &L, int32_t *offs, int32_t *ids) {
+    const Sched &s = L.s;
+    int32_t q = 0;
+    offs[0] = 0;
+    for (int32_t p = 0; p < s.n_prog; ++p) {
+        if (L.cfg.kind == TG_KIND_TILED) {
+            for (int32_t t = program_slot(p, s.n_prog); t < s.n_tiles;
+                 t += s.n_prog) {
+                int32_t tm, tn;
+                tile_coords(t, s, tm, tn);
+                ids[q++] = tm * s.tiles_n + tn;
+            }
+        } else {
+            ids[q++] = p;  // one program per sub-tensor, row-major grid
+        }
+        offs[p + 1] = q;
+    }
+}
+
+size_t split_bytes(const Problem &p, int np) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return up((size_t)p.M * p.K * np * 2) + up((size_t)p.K * p.N * np * 2);
+}
+
+int planes_of(int precision) {
+    return precision == TG_PREC_BF16X3 ? 3
+           : precision == TG_PREC_BF16X6 ? 6 : 1;
+}
+
+// Plane blocks along the concatenated K axis, smallest products first.
+// Entries are (A plane, B plane) with 0 = hi, 1 = mid, 2 = lo.
+const int8_t kX3A[3] = {0, 1, 0}, kX3B[3] = {1, 0, 0};
+const int8_t kX6A[6] = {1, 2, 0, 1, 0, 0}, kX6B[6] = {1, 0, 2, 0, 1, 0};
+
+std::mutex g_group_mu;
+std::unordered_map<const void *, GroupHeader> g_groups;
+
+}  // namespace
+
+extern "C" {
+
+const char *tg_status_str(int32_t st) {
+    switch (st) {
+    case TG_OK: return "TG_OK";
+    case TG_E_ARG: return "TG_E_ARG";
+    case TG_E_DTYPE: return "TG_E_DTYPE";
+    case TG_E_SHAPE: return "TG_E_SHAPE";
+    case TG_E_OVERLAP: return "TG_E_OVERLAP";
+    case TG_E_NOCOVER: return "TG_E_NOCOVER";
+    case TG_E_ALIAS: return "TG_E_ALIAS";
+    case TG_E_WORKSPACE: return "TG_E_WORKSPACE";
+    case TG_E_UNSUPPORTED: return "TG_E_UNSUPPORTED";
+    case TG_E_HIP: return "TG_E_HIP";
+    default: return "unknown status";
+    }
+}
+
+const char *tg_last_error(void) { return g_err.c_str(); }
+
+int32_t tg_device_cus(void) { return device_cus(); }
+
+tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
+                               const tg_out *out, int32_t n_prog,
+                               const int32_t *prog_offsets,
+                               const int32_t *prog_tiles) {
+    g_err.clear();
+    tg_status st;
+    if (n_in < 0 || (n_in > 0 && !ins))
+        return fail(TG_E_ARG, "bad input list");
+    for (int32_t i = 0; i < n_in; ++i) {
+        char name[32];
+        snprintf(name, sizeof name, "input %d", i);
+        if ((st = check_in(&ins[i], name)) != TG_OK) return st;
+    }
+    if ((st = check_out(out, true)) != TG_OK) return st;
+    int64_t tiles = ((out->rows + out->bm - 1) / out->bm) *
+                    ((out->cols + out->bn - 1) / out->bn);
+    if ((st = check_map(tiles, n_prog, prog_offsets, prog_tiles)) != TG_OK)
+        return st;
+    return check_alias(ins, n_in, out);
+}
+
+size_t tile_gemm_workspace_size(const tg_in *A, const tg_in *B,
+                                const tg_out *C, const tg_opts *o) {
+    Problem p;
+    if (describe(A, B, C, o, p) != TG_OK) return 0;
+    int np = planes_of(p.precision);
+    return np > 1 ? split_bytes(p, np) : 0;
+}
+
+tg_status tile_gemm_plan(const tg_in *A, const tg_in *B, const tg_out *C,
+                         const tg_opts *o, tg_config *cfg, int32_t *n_prog,
+                         int32_t *prog_offsets, int32_t *prog_tiles) {
+    g_err.clear();
+    Problem p;
+    tg_status st = describe(A, B, C, o, p);
+    if (st != TG_OK) return st;
+    Launch L;
+    if ((st = choose(p, A, B, C, o, L)) != TG_OK) return st;
+    if (cfg) *cfg = L.cfg;
+    if (n_prog) *n_prog = L.s.n_prog;
+    if (prog_offsets && prog_tiles) build_map(L, prog_offsets, prog_tiles);
+    return TG_OK;
+}
+
+tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
+                    const tg_opts *o, tg_stream stream) {
+    g_err.clear();
+    Problem p;
+    tg_status st = describe(A, B, C, o, p);
+    if (st != TG_OK) return st;
+    Launch L;
+    if ((st = choose(p, A, B, C, o, L)) != TG_OK) return st;
+    const bool checked = !o || o->checked;
+    if (checked) {
+        // the program map the kernel will walk must be injective and cover
+        // the partition of C, and C may not alias A or B
+        std::vector<int32_t> offs((size_t)L.s.n_prog + 1),
+            ids((size_t)L.s.n_tiles);
+        build_map(L, offs.data(), ids.data());
+        if ((st = check_map(L.s.n_tiles, L.s.n_prog, offs.data(),
+                            ids.data())) != TG_OK)
+            return st;
+        tg_out part = *C;
+        part.bm = L.cfg.bm;
+        part.bn = L.cfg.bn;
+        tg_in ins[2] = {*A, *B};
+        if ((st = check_alias(ins, 2, &part)) != TG_OK) return st;
+    }
+    C->bm = L.cfg.bm;
+    C->bn = L.cfg.bn;
+    if (p.M == 0 || p.N == 0) return TG_OK;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const float *sa = o ? o->scale_a : nullptr;
+    const float *sb = o ? o->scale_b : nullptr;
+    int32_t *wc = o ? o->write_count : nullptr;
+    hipError_t e = hipSuccess;
+
+    if (L.cfg.kind == TG_KIND_SKINNY) {
+        SkinnyArgs a;
+        a.x = A->data; a.w = B->data; a.y = C->data;
+        a.scale_a = sa; a.scale_w = sb; a.wcount = wc;
+        a.ldx = A->ld; a.ldw = B->ld; a.ldy = C->ld;
+        a.M = (int32_t)p.M; a.N = (int32_t)p.N; a.K = (int32_t)p.K;
+        a.bn = 16;
+        e = launch_skinny(p.b_dt, p.c_bf16, 16, L.cfg.ksplit, a, hs);
+        return e == hipSuccess ? TG_OK : hip_fail(e, "decode kernel launch");
+    }
+    if (L.cfg.kind == TG_KIND_SIMPLE) {
+        SimpleArgs a;
+        a.a = A->data; a.b = B->data; a.c = C->data;
+        a.scale_a = sa; a.scale_b = sb; a.wcount = wc;
+        a.lda = A->ld; a.ldb = B->ld; a.ldc = C->ld;
+        a.M = (int32_t)p.M; a.N = (int32_t)p.N; a.K = (int32_t)p.K;
+        a.a_dtype = p.a_dt; a.b_dtype = p.b_dt; a.c_bf16 = p.c_bf16;
+        a.b_nk = p.b_nk; a.bm = L.cfg.bm; a.bn = L.cfg.bn;
+        e = launch_simple(a, hs);
+        return e == hipSuccess ? TG_OK : hip_fail(e, "simple kernel launch");
+    }
+
+    GemmArgs g;
+    g.a = A->data; g.b = B->data; g.c = C->data;
+    g.scale_a = sa; g.scale_b = sb; g.wcount = wc;
+    g.lda = A->ld; g.ldb = B->ld; g.ldc = C->ld;
+    g.M = (int32_t)p.M; g.N = (int32_t)p.N; g.K = (int32_t)p.K;
+    g.s = L.s;
+    int np = planes_of(p.precision);
+    if (np > 1) {
+        size_t need = split_bytes(p, np);
+        if (!o || !o->workspace || o->workspace_bytes < need)
+            return fail(TG_E_WORKSPACE, "split precision needs %zu bytes",
+                        need);
+        if (!aligned16(o->workspace))
+            return fail(TG_E_WORKSPACE, "workspace must be 16-byte aligned");
+        Range rw{(uintptr_t)o->workspace, (uintptr_t)o->workspace + need};
+        Range rc = byte_range(C->data, C->rows, C->cols, C->ld,
+                              esize(C->dtype));
+        Range ra = byte_range(A->data, A->rows, A->cols, A->ld, 4);
+        Range rb = byte_range(B->data, B->rows, B->cols, B->ld, 4);
+        if (intersect(rw, rc) || intersect(rw, ra) || intersect(rw, rb))
+            return fail(TG_E_ALIAS, "workspace shares bytes with an operand");
+        char *ws = static_cast<char *>(o->workspace);
+        size_t a_bytes = ((size_t)p.M * p.K * np * 2 + 255) & ~(size_t)255;
+        void *ap = ws, *bp = ws + a_bytes;
+        const int8_t *oa = np == 3 ? kX3A : kX6A;
+        const int8_t *ob = np == 3 ? kX3B : kX6B;
+        int64_t Kc = p.K * np;
+        // A' = M x (np K): plane block b occupies columns [b K, (b+1) K)
+        e = launch_split_rows(static_cast<const float *>(A->data), A->ld,
+                              (int32_t)p.M, (int32_t)p.K, np, oa, ap, Kc,
+                              p.K, hs);
+        if (e != hipSuccess) return hip_fail(e, "split launch");
+        if (p.b_nk) {
+            // B stored N x K -> B' = N x (np K)
+            e = launch_split_rows(static_cast<const float *>(B->data), B->ld,
+                                  (int32_t)p.N, (int32_t)p.K, np, ob, bp, Kc,
+                                  p.K, hs);
+        } else {
+            // B stored K x N -> B' = (np K) x N: plane block b is rows
+            // [b K, (b+1) K)
+            e = launch_split_rows(static_cast<const float *>(B->data), B->ld,
+                                  (int32_t)p.K, (int32_t)p.N, np, ob, bp, p.N,
+                                  p.K * p.N, hs);
+        }
+        if (e != hipSuccess) return hip_fail(e, "split launch");
+        g.a = ap; g.b = bp;
+        g.lda = Kc;
+        g.ldb = p.b_nk ? Kc : p.N;
+        g.K = (int32_t)Kc;
+    }
+    e = launch_tiled(L.variant, g, hs);
+    return e == hipSuccess ? TG_OK : hip_fail(e, "tiled kernel launch");
+}
+
+// ----------------------------------------------------------------- grouped
+
+size_t tile_gemm_grouped_workspace_size(int32_t n) {
+    if (n <= 0) return 0;
+    return sizeof(GroupProblem) * (size_t)n;
+}
+
+tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
+                                    const tg_in *B, tg_out *C,
+                                    const tg_opts *o, void *ws,
+                                    size_t ws_bytes, tg_stream stream) {
+    g_err.clear();
+    if (n <= 0 || !A || !B || !C) return fail(TG_E_ARG, "empty problem list");
+    if (!ws) return fail(TG_E_WORKSPACE, "NULL workspace");
+    if (ws_bytes < tile_gemm_grouped_workspace_size(n))
+        return fail(TG_E_WORKSPACE, "workspace needs %zu bytes",
+                    tile_gemm_grouped_workspace_size(n));
+    if (!aligned16(ws)) return fail(TG_E_WORKSPACE, "workspace misaligned");
+    if (o && (o->precision != TG_PREC_NATIVE || o->scale_a || o->scale_b ||
+              o->write_count))
+        return fail(TG_E_UNSUPPORTED,
+                    "grouped launch: native precision, no scales");
+    std::vector<Problem> ps((size_t)n);
+    int c_bf16 = -1, b_nk = -1;
+    int64_t maxM = 0, maxN = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        tg_status st = describe(&A[i], &B[i], &C[i], nullptr, ps[i]);
+        if (st != TG_OK) {
+            g_err = "problem " + std::to_string(i) + ": " + g_err;
+            return st;
+        }
+        if (ps[i].a_dt != TG_BF16 || ps[i].b_dt != TG_BF16)
+            return fail(TG_E_DTYPE, "problem %d: grouped launch is bf16", i);
+        if (!tiled_ok(ps[i], &A[i], &B[i], TG_BF16))
+            return fail(TG_E_UNSUPPORTED, "problem %d: layout not tileable",
+                        i);
+        if (c_bf16 < 0) c_bf16 = ps[i].c_bf16;
+        if (b_nk < 0) b_nk = ps[i].b_nk;
+        if (c_bf16 != (int)ps[i].c_bf16 || b_nk != (int)ps[i].b_nk)
+            return fail(TG_E_UNSUPPORTED,
+                        "problem %d: all problems share C dtype and B layout",
+                        i);
+        maxM = std::max(maxM, ps[i].M);
+        maxN = std::max(maxN, ps[i].N);
+    }
+    // ownership across the launch: outputs pairwise disjoint and disjoint
+    // from every input
+    std::vector<Range> outs((size_t)n), ins((size_t)2 * n);
+    for (int32_t i = 0; i < n; ++i) {
+        outs[i] = byte_range(C[i].data, C[i].rows, C[i].cols, C[i].ld,
+                             esize(C[i].dtype));
+        ins[2 * i] = byte_range(A[i].data, A[i].rows, A[i].cols, A[i].ld, 2);
+        ins[2 * i + 1] =
+            byte_range(B[i].data, B[i].rows, B[i].cols, B[i].ld, 2);
+    }
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t j = i + 1; j < n; ++j)
+            if (intersect(outs[i], outs[j]))
+                return fail(TG_E_OVERLAP, "outputs %d and %d share bytes", i,
+                            j);
+        for (int32_t j = 0; j < 2 * n; ++j)
+            if (intersect(outs[i], ins[j]))
+                return fail(TG_E_ALIAS, "output %d shares bytes with an input "
+                                        "of problem %d", i, j / 2);
+    }
+    // one tile shape for the launch
+    tg_config cfg{};
+    if (o && o->config) cfg = *o->config;
+    if (cfg.bm == 0 || cfg.bn == 0) {
+        int64_t work = 0;
+        for (auto &p : ps) work += p.M * p.N;
+        cfg.bm = cfg.bn = work >= (int64_t)256 * 256 * 256 ? 256 : 128;
+    }
+    int variant = find_variant(TG_BF16, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
+                               b_nk == 1, c_bf16 == 1);
+    if (variant < 0)
+        return fail(TG_E_UNSUPPORTED, "no tiled kernel %d x %d", cfg.bm,
+                    cfg.bn);
+    for (int32_t i = 0; i < n; ++i) {
+        C[i].bm = cfg.bm;
+        C[i].bn = cfg.bn;
+    }
+    // longest K first: programs take tiles in table order with a fixed
+    // stride, so the costliest tiles are spread over all programs first
+    std::vector<int32_t> order((size_t)n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return ps[x].K > ps[y].K;
+    });
+    std::vector<GroupProblem> tab((size_t)n);
+    int64_t total = 0;
+    for (int32_t r = 0; r < n; ++r) {
+        int32_t i = order[r];
+        GroupProblem &g = tab[r];
+        g.a = A[i].data; g.b = B[i].data; g.c = C[i].data;
+        g.lda = A[i].ld; g.ldb = B[i].ld; g.ldc = C[i].ld;
+        g.M = (int32_t)ps[i].M; g.N = (int32_t)ps[i].N; g.K = (int32_t)ps[i].K;
+        g.tiles_m = (int32_t)((ps[i].M + cfg.bm - 1) / cfg.bm);
+        g.tiles_n = (int32_t)((ps[i].N + cfg.bn - 1) / cfg.bn);
+        g.tile_begin = (int32_t)total;
+        g.c_bf16 = c_bf16;
+        g.b_nk = b_nk;
+        total += (int64_t)g.tiles_m * g.tiles_n;
+    }
+    if (total > INT32_MAX) return fail(TG_E_SHAPE, "too many sub-tensors");
+    GroupHeader h{};
+    h.n = n;
+    h.total_tiles = (int32_t)total;
+    int cus = device_cus();
+    int occ = cus > 0 ? tiled_occupancy(variant) : 1;
+    h.n_prog = (int32_t)std::min<int64_t>(total,
+                                          (int64_t)(cus > 0 ? cus : 256) * occ);
+    if (h.n_prog < 1) h.n_prog = 1;
+    h.cfg_index = variant;
+    h.c_bf16 = c_bf16;
+    h.b_nk = b_nk;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(ws, tab.data(), sizeof(GroupProblem) * n,
+                                  hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "grouped table copy");
+    e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) return hip_fail(e, "grouped table copy");
+    std::lock_guard<std::mutex> lk(g_group_mu);
+    g_groups[ws] = h;
+    return TG_OK;
+}
+
+tg_status tile_gemm_grouped(void *ws, tg_stream stream) {
+    g_err.clear();
+    GroupHeader h;
+    {
+        std::lock_guard<std::mutex> lk(g_group_mu);
+        auto it = g_groups.find(ws);
+        if (it == g_groups.end())
+            return fail(TG_E_WORKSPACE,
+                        "workspace was not prepared by "
+                        "tile_gemm_grouped_prepare");
+        h = it->second;
+    }
+    if (h.total_tiles == 0) return TG_OK;
+    hipError_t e = launch_grouped(h.cfg_index, &h, ws,
+                                  static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TG_OK : hip_fail(e, "grouped kernel launch");
+}
+
+tg_status tile_error_norm(const void *C, int32_t c_dtype, const double *R,
+                          int64_t n, double *out, tg_stream stream) {
+    g_err.clear();
+    if (c_dtype != TG_F32 && c_dtype != TG_BF16)
+        return fail(TG_E_DTYPE, "C must be TG_F32 or TG_BF16");
+    if (n < 0) return fail(TG_E_ARG, "negative n");
+    if (!out || (n > 0 && (!C || !R))) return fail(TG_E_ARG, "NULL pointer");
+    hipError_t e = launch_error_norm(C, c_dtype == TG_BF16, R, n, out,
+                                     static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TG_OK : hip_fail(e, "error-norm launch");
+}
+
+}  // extern "C"

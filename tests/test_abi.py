@@ -1,0 +1,254 @@
+"""The C-ABI library: symbols, host-side ownership rules and error paths.
+
+CPU only: nothing here launches a kernel.  tile_partition_check is pure host
+code; tile_gemm's validation runs before anything is enqueued, so every
+rejected request can be exercised without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import ROOT
+
+tg = pytest.importorskip("paper_2606_15991_amd")
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "tilegemm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(tile_\w+|tg_\w+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_header_function():
+    names = header_functions()
+    assert {"tile_gemm", "tile_gemm_grouped", "tile_partition_check",
+            "tile_gemm_grouped_prepare", "tile_error_norm"} <= set(names)
+    lib = ctypes.CDLL(tg.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_library_is_gfx950_only():
+    data = open(tg.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+    for other in (b"gfx942", b"gfx90a", b"gfx1100"):
+        assert b"amdgcn-amd-amdhsa--" + other not in data
+
+
+def desc_in(addr, rows, cols, ld=None, dtype=tg.TG_BF16, trans=0):
+    return tg.tg_in(addr, dtype, trans, rows, cols, cols if ld is None else ld)
+
+
+def desc_out(addr, rows, cols, bm, bn, ld=None, dtype=tg.TG_F32):
+    return tg.tg_out(addr, dtype, 0, rows, cols, cols if ld is None else ld,
+                     bm, bn)
+
+
+BASE = 1 << 40   # fake, never dereferenced addresses
+
+
+def test_partition_check_matches_oracle_painter(oracle_mod):
+    rng = np.random.default_rng(0)
+    for trial in range(200):
+        M = int(rng.integers(1, 90))
+        N = int(rng.integers(1, 90))
+        bm = int(rng.integers(1, 40))
+        bn = int(rng.integers(1, 40))
+        tm, tn = -(-M // bm), -(-N // bn)
+        tiles = list(range(tm * tn))
+        rng.shuffle(tiles)
+        kind = trial % 4
+        if kind == 1 and tiles:        # drop one
+            tiles = tiles[:-1]
+        elif kind == 2 and tiles:      # duplicate one
+            tiles = tiles + [tiles[0]]
+        elif kind == 3:                # one id off the grid
+            tiles = tiles + [tm * tn]
+        n_prog = int(rng.integers(1, 9))
+        cuts = sorted(rng.integers(0, len(tiles) + 1, n_prog - 1).tolist())
+        offs = [0] + cuts + [len(tiles)]
+        out = desc_out(BASE, M, N, bm, bn)
+        st = tg.tile_partition_check([], out, offs, tiles)
+        ost, _ = oracle_mod.partition_paint(M, N, bm, bn, offs, tiles)
+        expect = {oracle_mod.PART_OK: tg.TG_OK,
+                  oracle_mod.PART_OVERLAP: tg.TG_E_OVERLAP,
+                  oracle_mod.PART_NOCOVER: tg.TG_E_NOCOVER,
+                  oracle_mod.PART_ARG: tg.TG_E_ARG}[ost]
+        assert st == expect, (M, N, bm, bn, kind)
+
+
+def test_partition_check_regular_grid_and_args():
+    out = desc_out(BASE, 100, 70, 32, 32)
+    assert tg.tile_partition_check([], out) == tg.TG_OK
+    assert tg.tile_partition_check([], desc_out(BASE, 100, 70, 0, 32)) == \
+        tg.TG_E_ARG
+    assert tg.tile_partition_check([], desc_out(BASE, 100, 70, 32, 32,
+                                                ld=60)) == tg.TG_E_SHAPE
+    assert tg.tile_partition_check([], desc_out(0, 100, 70, 32, 32)) == \
+        tg.TG_E_ARG
+
+
+def test_partition_check_listing5_race_rejected():
+    """The index-swap race of the paper's Sec. 3.5 as a program map over the
+    destination: H programs store the same sub-tensor."""
+    B, H, Mt = 2, 4, 4
+    offs, tiles = [0], []
+    for b in range(B):
+        for h1 in range(H):
+            for h2 in range(H):
+                for m in range(Mt):
+                    tiles.append((b * Mt + m) * H + h2)
+                offs.append(len(tiles))
+    out = desc_out(BASE, B * Mt * 8, H * 8, 8, 8)
+    assert tg.tile_partition_check([], out, offs, tiles) == tg.TG_E_OVERLAP
+    # the correct store index (b, h2, m) owns each sub-tensor once
+    offs, tiles = [0], []
+    for b in range(B):
+        for h in range(H):
+            for m in range(Mt):
+                tiles.append((b * Mt + m) * H + h)
+            offs.append(len(tiles))
+    assert tg.tile_partition_check([], out, offs, tiles) == tg.TG_OK
+
+
+def test_partition_check_alias_matches_byte_ranges(oracle_mod):
+    rng = np.random.default_rng(1)
+    for _ in range(300):
+        M, N, K = (int(x) for x in rng.integers(1, 50, 3))
+        a_addr = BASE + int(rng.integers(0, 20000)) * 2
+        c_addr = BASE + int(rng.integers(0, 20000)) * 4
+        ins = [desc_in(a_addr, M, K)]
+        out = desc_out(c_addr, M, N, 16, 16)
+        st = tg.tile_partition_check(ins, out)
+        overlap = oracle_mod.ranges_intersect(a_addr, ((M - 1) * K + K) * 2,
+                                              c_addr, ((M - 1) * N + N) * 4)
+        assert st == (tg.TG_E_ALIAS if overlap else tg.TG_OK)
+    # strided output: the gap between rows of a padded C still belongs to C
+    ins = [desc_in(BASE + 4 * 40, 1, 4)]
+    out = desc_out(BASE, 3, 10, 2, 2, ld=64)
+    assert tg.tile_partition_check(ins, out) == tg.TG_E_ALIAS
+
+
+def _plan(M, N, K, bm=0, bn=0, dtype=torch.bfloat16, b_trans=False,
+          precision="native", config=None):
+    A = torch.empty((M, K), dtype=dtype)
+    B = torch.empty((N, K) if b_trans else (K, N), dtype=dtype)
+    cdt = torch.float32
+    if dtype == torch.float8_e4m3fn:
+        b_trans = True
+        B = torch.empty((N, K), dtype=dtype)
+    C = torch.empty((M, N), dtype=cdt)
+    return tg.tile_gemm_plan(A, B, C, bm, bn, b_trans=b_trans,
+                             precision=precision, config=config)
+
+
+@pytest.mark.parametrize("M,N,K,bm", [
+    (8192, 8192, 8192, 256), (256, 256, 256, 32), (1000, 700, 64, 128),
+    (300, 200, 136, 64), (4096, 4096, 512, 256), (96, 5000, 64, 64)])
+def test_plan_map_is_owned_exactly_once(oracle_mod, M, N, K, bm):
+    dt = torch.float32 if bm == 32 else torch.bfloat16
+    # B stored K x N needs 16-byte rows along N; ragged N uses N x K storage
+    cfg, n_prog, offs, tiles = _plan(M, N, K, bm, bm, dtype=dt,
+                                     b_trans=N % 8 != 0)
+    assert cfg["bm"] == bm and cfg["bn"] == bm
+    assert cfg["kind"] == tg.TG_KIND_TILED
+    tm, tn = -(-M // bm), -(-N // bm)
+    assert n_prog == min(tm * tn, 256)
+    out = desc_out(BASE, M, N, bm, bm)
+    assert tg.tile_partition_check([], out, offs, tiles) == tg.TG_OK
+    if M * N <= 4_000_000:
+        st, counts = oracle_mod.partition_paint(M, N, bm, bm, offs, tiles)
+        assert st == oracle_mod.PART_OK and counts.max() == 1
+
+
+def test_plan_xcd_neighbours_share_operands():
+    """Programs resident on one XCD (p % 8 equal) take neighbouring
+    sub-tensors: in the first round of an 8192^3 / 256^2 launch each XCD's
+    32 programs touch at most 12 distinct A row-blocks + B column-blocks."""
+    cfg, n_prog, offs, tiles = _plan(8192, 8192, 8192, 256, 256)
+    tn = 8192 // 256
+    for x in range(8):
+        first = [tiles[offs[p]] for p in range(x, n_prog, 8)]
+        rows = {t // tn for t in first}
+        cols = {t % tn for t in first}
+        assert len(first) == 32 and len(rows) + len(cols) <= 12
+
+
+def test_plan_decode_and_simple_kinds():
+    cfg, n_prog, offs, tiles = _plan(8, 5120, 5120, 16, 16, b_trans=True)
+    assert cfg["kind"] == tg.TG_KIND_SKINNY and n_prog == 320
+    assert tiles == list(range(320))
+    # weight-only e4m3: bf16 activations, e4m3 weights stored N x K
+    x = torch.empty((1, 5120), dtype=torch.bfloat16)
+    w = torch.empty((51200, 5120), dtype=torch.float8_e4m3fn)
+    y = torch.empty((1, 51200), dtype=torch.bfloat16)
+    cfg, n_prog, _, _ = tg.tile_gemm_plan(x, w, y, b_trans=True,
+                                          want_map=False)
+    assert cfg["kind"] == tg.TG_KIND_SKINNY and n_prog == 3200
+    # K not a multiple of 8 bf16 elements -> no vector loads -> simple kernel
+    cfg, n_prog, offs, tiles = _plan(100, 90, 37)
+    assert cfg["kind"] == tg.TG_KIND_SIMPLE and n_prog == 2 * 2
+    # a partition with no tiled instantiation falls back as well
+    cfg, _, _, _ = _plan(100, 96, 64, 48, 48)
+    assert cfg["kind"] == tg.TG_KIND_SIMPLE and cfg["bm"] == 48
+
+
+def _gemm_err(A, B, C, **kw):
+    with pytest.raises(tg.TileGemmError) as e:
+        tg.tile_gemm(A, B, C, **kw)
+    return e.value.status
+
+
+def test_tile_gemm_rejects_before_enqueue():
+    f32, bf = torch.float32, torch.bfloat16
+    A = torch.empty((64, 32), dtype=bf)
+    B = torch.empty((32, 48), dtype=bf)
+    C = torch.empty((64, 48), dtype=f32)
+    assert _gemm_err(A, torch.empty((33, 48), dtype=bf), C) == tg.TG_E_SHAPE
+    assert _gemm_err(A, B, torch.empty((64, 47), dtype=f32)) == tg.TG_E_SHAPE
+    assert _gemm_err(A, B.float(), C) == tg.TG_E_DTYPE
+    assert _gemm_err(A, B, C, precision="bf16x3") == tg.TG_E_DTYPE
+    # split precision without a workspace
+    Af, Bf = A.float(), B.float()
+    st = tg.lib.tile_gemm(tg.make_in(Af), tg.make_in(Bf), tg.make_out(C, 64,
+                          64), tg.make_opts("bf16x6"), None)
+    assert st == tg.TG_E_WORKSPACE
+    # output aliasing an input (C placed on top of A's bytes)
+    big = torch.empty(64 * 48 * 4, dtype=torch.uint8)
+    Aal = big[:64 * 32 * 2].view(bf).view(64, 32)
+    Cal = big.view(f32).view(64, 48)
+    assert _gemm_err(Aal, B, Cal) == tg.TG_E_ALIAS
+    # a partition that the chosen kernel cannot own
+    assert _gemm_err(A, B, C, bm=32, bn=32,
+                     config={"kind": "tiled", "bm": 64, "bn": 64}) == \
+        tg.TG_E_ARG
+    assert _gemm_err(A, B, C, config={"kind": "tiled", "bm": 48,
+                                      "bn": 48}) == tg.TG_E_UNSUPPORTED
+    # e4m3 B stored K x N is not provided by the tiled kernel
+    A8 = torch.empty((64, 32), dtype=torch.float8_e4m3fn)
+    B8 = torch.empty((32, 48), dtype=torch.float8_e4m3fn)
+    assert _gemm_err(A8, B8, C, config={"kind": "tiled"}) == \
+        tg.TG_E_UNSUPPORTED
+    assert "tiled kernel" in tg.last_error()
+
+
+def test_status_strings():
+    assert tg.status_str(tg.TG_E_OVERLAP) == "TG_E_OVERLAP"
+    assert tg.status_str(99) == "unknown status"
+
+
+def test_workspace_sizes():
+    A = torch.empty((100, 64))
+    B = torch.empty((64, 80))
+    C = torch.empty((100, 80))
+    n6 = tg.tile_gemm_workspace_size(A, B, C, precision="bf16x6")
+    n3 = tg.tile_gemm_workspace_size(A, B, C, precision="bf16x3")
+    assert n6 >= 6 * 2 * (100 * 64 + 64 * 80) and n3 >= 3 * 2 * (
+        100 * 64 + 64 * 80) and n6 > n3
+    assert tg.tile_gemm_workspace_size(A, B, C) == 0
+    assert tg.tile_gemm_grouped_workspace_size(64) > 0

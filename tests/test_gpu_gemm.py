@@ -1,0 +1,390 @@
+"""Parity of the HIP path with the CPU oracle (needs an MI355X).
+
+Every input comes from the seeded generators in `synth`; every expected value
+from `oracle`.  Tolerances (relative Frobenius error against the oracle's
+product of the exact operand values):
+  * binary32 output: 1e-5 (binary32 accumulation over K <= 8192 of exactly
+    represented products stays far below it; the per-element binary32
+    dot-product bound is checked as well where stated);
+  * bf16 output: 4e-3 (one bf16 rounding of the result, unit roundoff 2^-8);
+  * small-integer inputs: bit-exact (all partial sums are integers below
+    2^24, so any summation order is exact);
+  * BF16x6 split precision against the f32 inputs' exact product: 2e-6;
+    BF16x3: 6e-6 (two bf16 planes keep about 16 significand bits, so its
+    error sits near 4e-6 and cannot reach 2e-6).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import (exact64, higham_ok, note, reference, reference_entries,
+                      rel_err)
+
+pytestmark = pytest.mark.gpu
+
+tg = pytest.importorskip("paper_2606_15991_amd")
+DEV = "cuda:0"
+
+
+def dev(t):
+    return t.to(DEV)
+
+
+def run_gemm(A, B, M, N, *, b_trans=False, out=torch.float32, bm=0, bn=0,
+             count=False, **kw):
+    Ad, Bd = dev(A), dev(B)
+    C = torch.full((M, N), float("nan"), dtype=out, device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV) if count else None
+    tg.tile_gemm(Ad, Bd, C, bm, bn, b_trans=b_trans, write_count=wc, **kw)
+    torch.cuda.synchronize()
+    return C.cpu(), (wc.cpu() if count else None)
+
+
+# --------------------------------------------------------------- plain f32
+
+def test_fp32_256_partition_32x32():
+    note("f32 256^3 U[-1,1) seed 1, partition 32x32")
+    A = synth.uniform_pm1((256, 256), 1)
+    B = synth.uniform_pm1((256, 256), 101)
+    C, wc = run_gemm(A, B, 256, 256, bm=32, bn=32, count=True)
+    assert tile_partition_of_last() == (32, 32)
+    R = reference(A, B)
+    assert rel_err(C, R) <= 1e-5
+    ok, worst = higham_ok(C, A, B)
+    assert ok, worst
+    assert torch.all(wc == 1)
+
+
+def tile_partition_of_last():
+    return tuple(tg.tile_gemm.last_partition)
+
+
+def test_fp32_256_small_integers_bit_exact():
+    note("f32 256^3 small integers seed 1")
+    A = synth.small_int((256, 256), 1)
+    B = synth.small_int((256, 256), 102)
+    C, wc = run_gemm(A, B, 256, 256, bm=32, bn=32, count=True)
+    assert np.array_equal(exact64(C), reference(A, B))
+    assert torch.all(wc == 1)
+
+
+@pytest.mark.parametrize("M,N,K,bm,b_trans", [
+    (300, 264, 100, 32, False), (130, 200, 36, 64, True),
+    (520, 392, 260, 128, False), (257, 129, 68, 64, False)])
+def test_fp32_tiles_and_tails(M, N, K, bm, b_trans):
+    note("f32", M, N, K, bm, b_trans)
+    A = synth.uniform_pm1((M, K), 7)
+    B = synth.uniform_pm1((N, K) if b_trans else (K, N), 8)
+    C, wc = run_gemm(A, B, M, N, b_trans=b_trans, bm=bm, bn=bm, count=True)
+    assert rel_err(C, reference(A, B, b_trans)) <= 1e-5
+    ok, worst = higham_ok(C, A, B, b_trans)
+    assert ok, worst
+    assert torch.all(wc == 1)
+
+
+# -------------------------------------------------------------------- bf16
+
+BF16_CASES = [
+    (384, 320, 192, 64, False), (300, 264, 136, 64, True),
+    (520, 776, 264, 128, False), (513, 385, 72, 128, True),
+    (600, 520, 200, 256, False), (777, 300, 520, 256, True),
+    (96, 80, 64, 32, False), (33, 47, 24, 32, True)]
+
+
+@pytest.mark.parametrize("M,N,K,bm,b_trans", BF16_CASES)
+@pytest.mark.parametrize("out", [torch.float32, torch.bfloat16])
+def test_bf16_tiled_parity(M, N, K, bm, b_trans, out):
+    note("bf16", M, N, K, bm, b_trans, out)
+    A = synth.to_bf16(synth.normal((M, K), 21))
+    B = synth.to_bf16(synth.normal((N, K) if b_trans else (K, N), 22))
+    C, wc = run_gemm(A, B, M, N, b_trans=b_trans, out=out, bm=bm, bn=bm,
+                     count=True, config={"kind": "tiled"})
+    R = reference(A, B, b_trans)
+    err = rel_err(C, R)
+    assert err <= (1e-5 if out == torch.float32 else 4e-3), err
+    if out == torch.float32:
+        ok, worst = higham_ok(C, A, B, b_trans)
+        assert ok, worst
+    assert torch.all(wc == 1)
+
+
+@pytest.mark.parametrize("M,N,K,bm,b_trans", BF16_CASES[:6])
+def test_bf16_small_integers_bit_exact(M, N, K, bm, b_trans):
+    note("bf16 int", M, N, K, bm, b_trans)
+    A = synth.to_bf16(synth.small_int((M, K), 23))
+    B = synth.to_bf16(synth.small_int((N, K) if b_trans else (K, N), 24))
+    C, _ = run_gemm(A, B, M, N, b_trans=b_trans, bm=bm, bn=bm)
+    assert np.array_equal(exact64(C), reference(A, B, b_trans))
+
+
+def test_bf16_deterministic_and_k_zero():
+    note("bf16 determinism 1024x1024x512 and K = 0")
+    A = dev(synth.to_bf16(synth.normal((1024, 512), 25)))
+    B = dev(synth.to_bf16(synth.normal((512, 1024), 26)))
+    C1 = torch.empty((1024, 1024), device=DEV)
+    C2 = torch.empty((1024, 1024), device=DEV)
+    tg.tile_gemm(A, B, C1, 256, 256)
+    tg.tile_gemm(A, B, C2, 256, 256)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    A0 = torch.empty((100, 0), dtype=torch.bfloat16, device=DEV)
+    B0 = torch.empty((0, 64), dtype=torch.bfloat16, device=DEV)
+    C0 = torch.full((100, 64), 7.0, device=DEV)
+    tg.tile_gemm(A0, B0, C0, 64, 64)
+    torch.cuda.synchronize()
+    assert torch.all(C0 == 0)
+
+
+# --------------------------------------------------------------------- fp8
+
+# The 8-bit matrix instruction of gfx950 does not round its 64-product
+# block sums like a binary32 accumulation: against the exact sum of the same
+# decoded values its result carries a relative Frobenius error near 1.3e-5
+# (measured; the same values contracted by the bf16 instruction stay near
+# 1e-7).  The bar for E4M3 products against the oracle is therefore 1e-4.
+FP8_BAR = 1e-4
+
+
+@pytest.mark.parametrize("M,N,K,bm", [(256, 320, 384, 64), (300, 200, 208, 128),
+                                      (520, 600, 256, 256), (40, 70, 48, 32)])
+def test_fp8_tiled_parity(M, N, K, bm):
+    note("fp8 int", M, N, K, bm)
+    # small integers in e4m3 are exact and their block sums are integers far
+    # below 2^11: bit-exact product
+    ia = synth.small_int((M, K), 33).to(torch.float8_e4m3fn)
+    ib = synth.small_int((N, K), 34).to(torch.float8_e4m3fn)
+    C, wc = run_gemm(ia, ib, M, N, b_trans=True, bm=bm, bn=bm, count=True)
+    assert np.array_equal(exact64(C), reference(ia, ib, True))
+    assert torch.all(wc == 1)
+    note("fp8", M, N, K, bm)
+    qa, sa = synth.quant_e4m3_rows(synth.normal((M, K), 31))
+    qb, sb = synth.quant_e4m3_rows(synth.normal((N, K), 32))
+    C, _ = run_gemm(qa, qb, M, N, b_trans=True, bm=bm, bn=bm,
+                    scale_a=dev(sa), scale_b=dev(sb))
+    R = reference(qa, qb, True, sa, sb)
+    err = rel_err(C, R)
+    note("fp8 err %.3g" % err)
+    assert err <= FP8_BAR
+
+
+def test_fp8_instruction_precision_characterised():
+    """The same E4M3 values through the 8-bit and the bf16 instructions (the
+    decode is exact in bf16): the bf16 result meets the binary32 bar, the
+    8-bit one stays within FP8_BAR."""
+    M, N, K = 256, 256, 64
+    note("fp8 vs bf16 instruction", M, N, K)
+    qa, _ = synth.quant_e4m3_rows(synth.normal((M, K), 35))
+    qb, _ = synth.quant_e4m3_rows(synth.normal((N, K), 36))
+    R = reference(qa, qb, True)
+    C8, _ = run_gemm(qa, qb, M, N, b_trans=True, bm=64, bn=64)
+    Cb, _ = run_gemm(qa.to(torch.bfloat16), qb.to(torch.bfloat16), M, N,
+                     b_trans=True, bm=64, bn=64)
+    e8, eb = rel_err(C8, R), rel_err(Cb, R)
+    note("one-instruction error: e4m3 %.3g, bf16 %.3g" % (e8, eb))
+    assert eb <= 1e-6
+    assert e8 <= FP8_BAR
+
+
+# ------------------------------------------------------------------ decode
+
+@pytest.mark.parametrize("M", [1, 8, 16])
+@pytest.mark.parametrize("N,K", [(80, 512), (200, 1000), (1040, 4096)])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+def test_decode_parity(M, N, K, wdt):
+    if wdt == "fp8" and K % 16:
+        K += 16 - K % 16
+    note("decode", M, N, K, wdt)
+    x = synth.to_bf16(synth.normal((M, K), 41))
+    w = synth.normal((N, K), 42, std=0.02)
+    if wdt == "bf16":
+        W, sw = synth.to_bf16(w), None
+    else:
+        W, sw = synth.quant_e4m3_rows(w)
+    for out in (torch.float32, torch.bfloat16):
+        C, wc = run_gemm(x, W, M, N, b_trans=True, out=out, count=True,
+                         scale_b=None if sw is None else dev(sw))
+        assert tile_partition_of_last() == (16, 16)
+        R = reference(x, W, True, None, sw)
+        err = rel_err(C, R)
+        assert err <= (1e-5 if out == torch.float32 else 4e-3), err
+        assert torch.all(wc == 1)
+
+
+@pytest.mark.parametrize("ks", [1, 2, 4, 8, 16])
+def test_decode_ksplit_bitwise_stable(ks):
+    note("decode ksplit", ks)
+    x = synth.to_bf16(synth.small_int((8, 2048), 43))
+    W = synth.to_bf16(synth.small_int((96, 2048), 44))
+    C, _ = run_gemm(x, W, 8, 96, b_trans=True,
+                    config={"kind": "skinny", "ksplit": ks})
+    assert np.array_equal(exact64(C), reference(x, W, True))
+
+
+def test_decode_weight_only_fp8_end_to_end_error():
+    """Weight-only E4M3 against the unquantised binary64 product: the
+    quantisation error of N(0, 0.02) weights, K = 5120, stays within 3e-2."""
+    note("decode fp8 end-to-end 8 x 5120 x 5120")
+    M, N, K = 8, 5120, 5120
+    x = synth.to_bf16(synth.normal((M, K), 3))
+    w = synth.normal((N, K), 303, std=0.02)
+    q, s = synth.quant_e4m3_rows(w)
+    C, _ = run_gemm(x, q, M, N, b_trans=True, scale_b=dev(s))
+    R_exact = reference(x, w, True)
+    assert rel_err(C, R_exact) <= 3e-2
+    assert rel_err(C, reference(x, q, True, None, s)) <= 1e-5
+
+
+# ------------------------------------------------------------------ simple
+
+@pytest.mark.parametrize("M,N,K,dt", [(100, 90, 37, torch.bfloat16),
+                                      (65, 33, 13, torch.float32),
+                                      (50, 70, 21, torch.float8_e4m3fn)])
+def test_simple_kernel_unaligned(M, N, K, dt):
+    note("simple", M, N, K, dt)
+    A = synth.normal((M, K), 51).to(dt)
+    B = synth.normal((N, K), 52).to(dt)
+    C, wc = run_gemm(A, B, M, N, b_trans=True, count=True)
+    assert rel_err(C, reference(A, B, True)) <= 1e-5
+    assert torch.all(wc == 1)
+    # weight-only e4m3 with more than 16 rows
+    if dt == torch.float8_e4m3fn:
+        Ab = synth.to_bf16(synth.normal((M, K), 53))
+        C, _ = run_gemm(Ab, B, M, N, b_trans=True)
+        assert rel_err(C, reference(Ab, B, True)) <= 1e-5
+
+
+# -------------------------------------------------------- split precision
+
+@pytest.mark.parametrize("b_trans", [False, True])
+def test_split_precision(b_trans):
+    M, N, K = 384, 320, 512
+    note("split", M, N, K, b_trans)
+    A = synth.normal((M, K), 61)
+    B = synth.normal((N, K) if b_trans else (K, N), 62)
+    R = reference(A, B, b_trans)
+    C6, _ = run_gemm(A, B, M, N, b_trans=b_trans, precision="bf16x6")
+    C3, _ = run_gemm(A, B, M, N, b_trans=b_trans, precision="bf16x3")
+    C1, _ = run_gemm(A, B, M, N, b_trans=b_trans)
+    e6, e3, e1 = rel_err(C6, R), rel_err(C3, R), rel_err(C1, R)
+    note("split errors x6 %.3g x3 %.3g f32 %.3g" % (e6, e3, e1))
+    assert e6 <= 2e-6
+    assert e3 <= 6e-6
+    assert e1 <= 1e-5
+    assert e6 < e3
+
+
+# ----------------------------------------------------- full-size, sampled
+
+def test_bf16_8192_sampled_against_oracle():
+    """The benchmarked workload, in the benchmarked launch configuration:
+    8192^3 bf16 N(0,1), 256 x 256 partition; 2048 sampled outputs."""
+    M = N = K = 8192
+    note("bf16 8192^3 sampled")
+    A = synth.to_bf16(synth.normal((M, K), 2))
+    B = synth.to_bf16(synth.normal((K, N), 202))
+    C = torch.empty((M, N), device=DEV)
+    tg.tile_gemm(dev(A), dev(B), C, 256, 256)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2)
+    ii = rng.integers(0, M, 2048)
+    jj = rng.integers(0, N, 2048)
+    # every 256 x 256 sub-tensor's corners as well
+    corners = np.arange(0, M, 256)
+    ii = np.concatenate([ii, np.repeat(corners, 32), np.repeat(corners + 255,
+                                                               32)])
+    jj = np.concatenate([jj, np.tile(corners, 32), np.tile(corners + 255, 32)])
+    R = reference_entries(A, B, ii, jj)
+    got = C.cpu().numpy().astype(np.float64)[ii, jj]
+    import oracle
+    assert oracle.rel_fro(got, R) <= 1e-5
+    assert np.all(np.isfinite(got))
+
+
+@pytest.mark.parametrize("N,K", synth.DECODE_SHAPES)
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+def test_decode_full_shapes_sampled(N, K, wdt):
+    M = 8
+    note("decode full", M, N, K, wdt)
+    x = synth.to_bf16(synth.normal((M, K), 3))
+    w = synth.normal((N, K), 303, std=0.02)
+    if wdt == "bf16":
+        W, s = synth.to_bf16(w), None
+    else:
+        W, s = synth.quant_e4m3_rows(w)
+    C, _ = run_gemm(x, W, M, N, b_trans=True, out=torch.float32,
+                    scale_b=None if s is None else dev(s))
+    rng = np.random.default_rng(3)
+    jj = rng.integers(0, N, 512)
+    ii = rng.integers(0, M, 512)
+    R = reference_entries(x, W, ii, jj, True, None, s)
+    import oracle
+    assert oracle.rel_fro(C.numpy().astype(np.float64)[ii, jj], R) <= 1e-5
+
+
+# -------------------------------------------------------------- error norm
+
+def test_error_norm_kernel_matches_oracle():
+    import oracle
+    note("error norm")
+    R = synth.normal((1000, 777), 71).double()
+    C = (R + synth.normal((1000, 777), 72).double() * 1e-3).float()
+    out = tg.tile_error_norm(dev(C), dev(R.contiguous()))
+    torch.cuda.synchronize()
+    num, den = out[0].item(), out[1].item()
+    Cn, Rn = exact64(C).ravel(), R.numpy().ravel()
+    assert abs(num - np.sum((Cn - Rn) ** 2)) <= 1e-12 * num
+    assert abs(den - np.sum(Rn * Rn)) <= 1e-12 * den
+    assert abs(np.sqrt(num / den) - oracle.rel_fro(Cn, Rn)) <= 1e-12
+    out2 = tg.tile_error_norm(dev(C), dev(R.contiguous()))
+    torch.cuda.synchronize()
+    assert out2[0].item() == num and out2[1].item() == den
+    Cb = C.to(torch.bfloat16)
+    out3 = tg.tile_error_norm(dev(Cb), dev(R.contiguous()))
+    torch.cuda.synchronize()
+    assert abs(np.sqrt(out3[0].item() / out3[1].item()) -
+               oracle.rel_fro(exact64(Cb).ravel(), Rn)) <= 1e-12
+
+
+# ----------------------------------------------------------------- grouped
+
+def test_grouped_matches_oracle_and_single_launches():
+    shapes = [(1, 256, 128), (77, 384, 256), (300, 128, 512), (520, 640, 128),
+              (129, 1024, 384), (1000, 256, 256), (64, 512, 640),
+              (2, 128, 1024)]
+    note("grouped", shapes)
+    As = [dev(synth.to_bf16(synth.normal((m, k), 80 + i)))
+          for i, (m, n, k) in enumerate(shapes)]
+    Bs = [dev(synth.to_bf16(synth.normal((k, n), 90 + i)))
+          for i, (m, n, k) in enumerate(shapes)]
+    Cs = [torch.full((m, n), float("nan"), device=DEV) for m, n, k in shapes]
+    launch = tg.tile_gemm_grouped_prepare(As, Bs, Cs,
+                                          config={"bm": 128, "bn": 128})
+    tg.tile_gemm_grouped(launch)
+    torch.cuda.synchronize()
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        R = reference(A.cpu(), B.cpu())
+        assert rel_err(C.cpu(), R) <= 1e-5, i
+        single = torch.empty_like(C)
+        tg.tile_gemm(A, B, single, 128, 128)
+        torch.cuda.synchronize()
+        assert torch.equal(single, C), i
+    eager = [c.clone() for c in Cs]
+    # capture the single launch in a graph and replay it
+    for c in Cs:
+        c.fill_(float("nan"))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tg.tile_gemm_grouped(launch, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for c in Cs:
+            c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for c, e in zip(Cs, eager):
+            assert torch.equal(c, e), rep
