@@ -7,19 +7,28 @@
 // into its own BM x BN sub-tensor only.  A and B are read-only.
 //
 // gfx950 design:
-//   * every K tile is 128 bytes deep (64 bf16, 32 f32 or 128 e4m3), so both
-//     operands live in LDS as [rows][128 B] with the 16-byte chunk index
-//     XOR-swizzled by (row & 7): 16-byte reads and writes of 8 consecutive
-//     rows hit 8 distinct chunk positions, i.e. all 32 banks once;
-//   * B is held n-major in LDS (k contiguous, like A); a B stored K x N is
-//     transposed in registers, 8 x 8 (bf16) or 4 x 4 (f32) blocks at a time,
-//     between the coalesced 16-byte global loads and the LDS writes;
-//   * two LDS stages: while the MFMAs consume stage s, the next K tile is in
-//     flight from global memory into registers and is written into stage
-//     s ^ 1 afterwards; one barrier per K tile;
-//   * rows of A beyond M and columns of B beyond N are clamped to valid
-//     addresses (their products only reach outputs that are never stored),
-//     so full K tiles carry no predicates; the K tail is zero-filled.
+//   * every K tile is 128 bytes deep (64 bf16, 32 f32 or 128 e4m3);
+//   * k-contiguous operands (A, and B stored N x K) live in LDS as
+//     [rows][128 B] with the 16-byte chunk index XOR-swizzled by (row & 7),
+//     so the 16-byte fragment reads of 8 consecutive rows hit 8 distinct
+//     chunk positions;
+//   * bf16 and e4m3 tiles move from HBM to LDS with direct buffer->LDS
+//     loads (no staging registers, no LDS write instructions): lane l of a
+//     wavefront writes LDS bytes [16 l, 16 l + 16) of a 1 KiB block, so each
+//     lane fetches the global chunk that the swizzle assigns to that
+//     position; one buffer descriptor per operand and K tile, offsets past
+//     its end (rows beyond M or N, K beyond the tail) load zeros;
+//   * a bf16 B stored K x N stays k-major in LDS ([BK][BN], chunk index
+//     XOR-swizzled by 2 (k & 3)) and is read with the transposing LDS read,
+//     which hands each lane four consecutive k of one column;
+//   * two LDS stages: the next K tile streams into stage s ^ 1 while the
+//     MFMAs consume stage s; one barrier per K tile; the first stage of the
+//     program's next sub-tensor is fetched while the current one is stored;
+//   * f32 tiles go through registers (B stored K x N transposed 4 x 4 in
+//     registers), pipelined the same way;
+//   * in the f32 register path rows of A beyond M and columns of B beyond N
+//     are clamped to valid addresses (their products only reach outputs that
+//     are never stored) and the K tail is zero-filled.
 #include <atomic>
 
 #include "tg_device.hpp"
@@ -27,6 +36,10 @@
 
 namespace tg {
 namespace {
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
 
 template <int DT>
 struct DtypeTraits;
@@ -51,82 +64,188 @@ struct Cfg {
     static constexpr int ES = DtypeTraits<DT>::ES;
     static constexpr int EPC = 16 / ES;         // elements per 16-byte chunk
     static constexpr int BK = 128 / ES;         // K elements per K tile
-    static constexpr int THREADS = WM * WN * 64;
+    static constexpr int NW = WM * WN;          // wavefronts
+    static constexpr int THREADS = NW * 64;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int FM = TM / 32, FN = TN / 32;
+    static constexpr bool DIRECT = ES <= 2;     // direct global->LDS loads
+    static constexpr bool B_KMAJOR = !BNK && ES == 2;  // [BK][BN] in LDS
+    static constexpr int RB = BN * ES;          // bytes per k-major B row
+    static constexpr int CPR = RB / 16;         // chunks per k-major B row
     static constexpr int A_CH = BM * 8 / THREADS;   // A chunks per thread
-    static constexpr int B_CH = BN * 8 / THREADS;   // B chunks (n-major B)
-    // k-major B: EPC x EPC blocks, (BK / EPC) * (BN / EPC) of them
+    static constexpr int B_CH = BN * 8 / THREADS;   // B chunks per thread
+    // f32 B stored K x N: EPC x EPC blocks, (BK / EPC) * (BN / EPC) of them
     static constexpr int B_BLK = (BK / EPC) * (BN / EPC);
     static constexpr int B_BLK_PT = (B_BLK + THREADS - 1) / THREADS;
     static constexpr int STAGE = (BM + BN) * 128;   // bytes per LDS stage
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
     static_assert((BM * 8) % THREADS == 0, "A chunk split");
+    static_assert((BN * 8) % THREADS == 0, "B chunk split");
+    static_assert((BM / 8) % NW == 0 && (BN / 8) % NW == 0, "1 KiB blocks");
     static_assert(BNK || DT != TG_FP8_E4M3, "e4m3 B must be stored N x K");
-    static_assert(!BNK || (BN * 8) % THREADS == 0, "B chunk split");
+    static_assert(!B_KMAJOR || CPR >= 4, "k-major B rows of >= 64 bytes");
 };
 
 __device__ __forceinline__ int swz(int row, int chunk) {
     return row * 128 + ((chunk ^ (row & 7)) << 4);
 }
 
+// Chunk permutation of k-major B rows: rows k .. k+3 of a 16-lane
+// transposing read land in four distinct 32-byte bank groups.
 template <class C>
-struct Tile {
-    // registers holding the next K tile between its global load and its
-    // LDS write
+__device__ __forceinline__ int swz_kmajor(int k) {
+    return (2 * (k & 3)) & (C::CPR - 1);
+}
+
+__device__ __forceinline__ void wait_vmem() {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+// One owned sub-tensor as the kernels see it.
+struct Job {
+    const char *a;
+    const char *b;
+    void *c;
+    const float *scale_a;
+    const float *scale_b;
+    int32_t *wcount;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K;
+    int32_t m0, n0;
+};
+
+// ------------------------------------------------------------ tile loads
+
+// Buffer resource of `bytes` bytes at `base` (raw buffer, no stride).
+// Lanes whose offset is at or beyond `bytes` read zeros; the direct load
+// then writes those zeros into LDS.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base,
+                                                           uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base),
+                                             (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+constexpr uint32_t kOutOfRange = 0x80000000u;
+
+__device__ __forceinline__ void buf_to_lds(__amdgpu_buffer_rsrc_t r,
+                                           char *dst, uint32_t voff) {
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void *)dst, 16, voff, 0,
+                                             0, 0);
+}
+
+__device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
+    return b <= 0 ? 0u : (b >= 0x7fffffff ? 0x7fffffffu : (uint32_t)b);
+}
+
+// Direct HBM -> LDS issue of K tile k0 of one owned sub-tensor.  Each lane
+// fetches the 16-byte chunk that the LDS swizzle places at its position.
+// Rows beyond M / N and K beyond the operand read as zeros (out-of-range
+// buffer offsets), so the K tail needs no separate path.
+template <class C>
+__device__ __forceinline__ void issue_direct(const Job &j, char *stage,
+                                             int k0, int wave, int lane) {
+    const int rsub = lane >> 3;
+    const int kc = (lane & 7) ^ rsub;
+    const bool kin = k0 + kc * C::EPC < j.K;
+    {
+        // A rows m0.. : descriptor from (m0, k0); rows >= M are past its end
+        const char *base = j.a + ((int64_t)j.m0 * j.lda + k0) * C::ES;
+        const uint32_t nrec =
+            sat_bytes(((int64_t)(j.M - j.m0) * j.lda - k0) * C::ES);
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
+        const uint32_t off0 =
+            (uint32_t)(((wave * 8 + rsub) * j.lda + kc * C::EPC) * C::ES);
+        const uint32_t step = (uint32_t)(C::NW * 8 * j.lda * C::ES);
+#pragma unroll
+        for (int i = 0; i < C::BM / 8 / C::NW; ++i)
+            buf_to_lds(r, stage + (i * C::NW + wave) * 1024,
+                       kin ? off0 + i * step : kOutOfRange);
+    }
+    char *Bs = stage + C::BM * 128;
+    if constexpr (!C::B_KMAJOR) {
+        const char *base = j.b + ((int64_t)j.n0 * j.ldb + k0) * C::ES;
+        const uint32_t nrec =
+            sat_bytes(((int64_t)(j.N - j.n0) * j.ldb - k0) * C::ES);
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
+        const uint32_t off0 =
+            (uint32_t)(((wave * 8 + rsub) * j.ldb + kc * C::EPC) * C::ES);
+        const uint32_t step = (uint32_t)(C::NW * 8 * j.ldb * C::ES);
+#pragma unroll
+        for (int i = 0; i < C::BN / 8 / C::NW; ++i)
+            buf_to_lds(r, Bs + (i * C::NW + wave) * 1024,
+                       kin ? off0 + i * step : kOutOfRange);
+    } else {
+        // k-major B: descriptor from (k0, n0); rows k >= K are past its end,
+        // columns >= N are masked per lane
+        const char *base = j.b + ((int64_t)k0 * j.ldb + j.n0) * C::ES;
+        const uint32_t nrec =
+            sat_bytes(((int64_t)(j.K - k0) * j.ldb - j.n0) * C::ES);
+        const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
+#pragma unroll
+        for (int i = 0; i < C::BN / 8 / C::NW; ++i) {
+            const int gi = i * C::NW + wave;
+            const int off = gi * 1024 + lane * 16;
+            const int k = off / C::RB;
+            const int lc = ((off % C::RB) >> 4) ^ swz_kmajor<C>(k);
+            const bool nin = j.n0 + lc * C::EPC < j.N;
+            buf_to_lds(r, Bs + gi * 1024,
+                       nin ? (uint32_t)((k * j.ldb + lc * C::EPC) * C::ES)
+                           : kOutOfRange);
+        }
+    }
+}
+
+// Register-staged K tile of the f32 path.  load() issues the global reads,
+// store() writes LDS.
+template <class C>
+struct RegTile {
     uint4 ra[C::A_CH];
+    static_assert(!C::DIRECT, "register staging is the f32 path");
     uint4 rb[C::BNK ? C::B_CH : C::B_BLK_PT * C::EPC];
 
     template <bool MASK>
-    __device__ __forceinline__ void load(const GemmArgs &g, int m0, int n0,
-                                         int k0, int tid) {
-        const char *A = static_cast<const char *>(g.a);
-        const char *B = static_cast<const char *>(g.b);
+    __device__ __forceinline__ void load(const Job &j, int k0, int tid) {
 #pragma unroll
         for (int i = 0; i < C::A_CH; ++i) {
-            int q = i * C::THREADS + tid;
-            int r = q >> 3, kc = q & 7;
-            int row = m0 + r;
-            row = row < g.M ? row : g.M - 1;
-            int k = k0 + kc * C::EPC;
-            if (MASK && k >= g.K) {
+            const int q = i * C::THREADS + tid;
+            int row = j.m0 + (q >> 3);
+            row = row < j.M ? row : j.M - 1;
+            const int k = k0 + (q & 7) * C::EPC;
+            if (MASK && k >= j.K)
                 ra[i] = uint4{0, 0, 0, 0};
-            } else {
-                ra[i] = ld16(A + ((int64_t)row * g.lda + k) * C::ES);
-            }
+            else
+                ra[i] = ld16(j.a + ((int64_t)row * j.lda + k) * C::ES);
         }
         if constexpr (C::BNK) {
 #pragma unroll
             for (int i = 0; i < C::B_CH; ++i) {
-                int q = i * C::THREADS + tid;
-                int r = q >> 3, kc = q & 7;
-                int row = n0 + r;
-                row = row < g.N ? row : g.N - 1;
-                int k = k0 + kc * C::EPC;
-                if (MASK && k >= g.K) {
+                const int q = i * C::THREADS + tid;
+                int row = j.n0 + (q >> 3);
+                row = row < j.N ? row : j.N - 1;
+                const int k = k0 + (q & 7) * C::EPC;
+                if (MASK && k >= j.K)
                     rb[i] = uint4{0, 0, 0, 0};
-                } else {
-                    rb[i] = ld16(B + ((int64_t)row * g.ldb + k) * C::ES);
-                }
+                else
+                    rb[i] = ld16(j.b + ((int64_t)row * j.ldb + k) * C::ES);
             }
         } else {
             constexpr int NB = C::BN / C::EPC;
 #pragma unroll
             for (int i = 0; i < C::B_BLK_PT; ++i) {
-                int blk = i * C::THREADS + tid;
+                const int blk = i * C::THREADS + tid;
                 if (C::B_BLK % C::THREADS != 0 && blk >= C::B_BLK) break;
-                int kb = blk / NB, nb = blk % NB;
-                int col = n0 + nb * C::EPC;
-                col = col < g.N ? col : g.N - C::EPC;
+                const int kb = blk / NB, nb = blk % NB;
+                int col = j.n0 + nb * C::EPC;
+                col = col < j.N ? col : j.N - C::EPC;
 #pragma unroll
                 for (int r = 0; r < C::EPC; ++r) {
-                    int k = k0 + kb * C::EPC + r;
-                    if (MASK && k >= g.K) {
+                    const int k = k0 + kb * C::EPC + r;
+                    if (MASK && k >= j.K)
                         rb[i * C::EPC + r] = uint4{0, 0, 0, 0};
-                    } else {
+                    else
                         rb[i * C::EPC + r] =
-                            ld16(B + ((int64_t)k * g.ldb + col) * C::ES);
-                    }
+                            ld16(j.b + ((int64_t)k * j.ldb + col) * C::ES);
                 }
             }
         }
@@ -137,53 +256,63 @@ struct Tile {
         char *Bs = stage + C::BM * 128;
 #pragma unroll
         for (int i = 0; i < C::A_CH; ++i) {
-            int q = i * C::THREADS + tid;
+            const int q = i * C::THREADS + tid;
             st16(As + swz(q >> 3, q & 7), ra[i]);
         }
         if constexpr (C::BNK) {
 #pragma unroll
             for (int i = 0; i < C::B_CH; ++i) {
-                int q = i * C::THREADS + tid;
+                const int q = i * C::THREADS + tid;
                 st16(Bs + swz(q >> 3, q & 7), rb[i]);
             }
         } else {
+            // f32 B stored K x N: 4 x 4 blocks (rows k, columns n) become
+            // chunks (n, k .. k+3)
             constexpr int NB = C::BN / C::EPC;
 #pragma unroll
             for (int i = 0; i < C::B_BLK_PT; ++i) {
-                int blk = i * C::THREADS + tid;
+                const int blk = i * C::THREADS + tid;
                 if (C::B_BLK % C::THREADS != 0 && blk >= C::B_BLK) break;
-                int kb = blk / NB, nb = blk % NB;
-                const uint4 *r = &rb[i * C::EPC];
-                if constexpr (C::ES == 2) {
-                    // 8 x 8 bf16 block: rows k, columns n -> chunks (n, k..k+7)
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(r);
+                const int kb = blk / NB, nb = blk % NB;
+                const uint32_t *w =
+                    reinterpret_cast<const uint32_t *>(&rb[i * C::EPC]);
 #pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        uint32_t o[4];
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            uint32_t x = w[(2 * j) * 4 + c / 2];
-                            uint32_t y = w[(2 * j + 1) * 4 + c / 2];
-                            o[j] = (c & 1) ? ((x >> 16) | (y & 0xffff0000u))
-                                           : ((x & 0xffffu) | (y << 16));
-                        }
-                        st16(Bs + swz(nb * 8 + c, kb),
-                             uint4{o[0], o[1], o[2], o[3]});
-                    }
-                } else {
-                    // 4 x 4 f32 block
-                    const uint32_t *w = reinterpret_cast<const uint32_t *>(r);
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        st16(Bs + swz(nb * 4 + c, kb),
-                             uint4{w[0 * 4 + c], w[1 * 4 + c], w[2 * 4 + c],
-                                   w[3 * 4 + c]});
-                    }
-                }
+                for (int c = 0; c < 4; ++c)
+                    st16(Bs + swz(nb * 4 + c, kb),
+                         uint4{w[0 * 4 + c], w[1 * 4 + c], w[2 * 4 + c],
+                               w[3 * 4 + c]});
             }
         }
     }
 };
+
+// ---------------------------------------------------------------- compute
+
+// B operand of the 32x32x16 bf16 instruction from a k-major B stage:
+// two transposing reads.  In each 16-lane group, lane r names row
+// k = kb + r / 4 at columns c0 + 4 (r % 4) .. +3, and lane i of the group
+// receives column c0 + i at rows kb .. kb + 3.
+template <class C>
+__device__ __forceinline__ i32x4 read_b_kmajor(const char *Bs, int kk,
+                                               int col0, int lane) {
+    const int g = lane >> 4, r = lane & 15;
+    const int half = g >> 1, cg = g & 1;
+    const int n = col0 + cg * 16 + 4 * (r & 3);
+    i32x4 out;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int k = kk * 16 + half * 8 + q * 4 + (r >> 2);
+        const char *p = Bs + k * C::RB +
+                        (((n >> 3) ^ swz_kmajor<C>(k)) << 4) + ((n & 7) << 1);
+        const s16x4 v = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_s16x4 *)(p));
+        const uint32_t v0 = (uint16_t)v[0], v1 = (uint16_t)v[1];
+        const uint32_t v2 = (uint16_t)v[2], v3 = (uint16_t)v[3];
+        out[2 * q] = (int)(v0 | (v1 << 16));
+        out[2 * q + 1] = (int)(v2 | (v3 << 16));
+    }
+    return out;
+}
 
 template <class C>
 __device__ __forceinline__ void compute_stage(const char *stage, int wm,
@@ -193,28 +322,51 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
     const char *Bs = stage + C::BM * 128;
     const int r = lane & 31, half = lane >> 5;
     if constexpr (C::DTYPE == TG_BF16 || C::DTYPE == TG_F32) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        // fragments of step kk + 1 are read while the MFMAs of step kk run
+        i32x4 af[2][C::FM], bfr[2][C::FN];
+        auto load = [&](int kk, int s) {
             const int c = 2 * kk + half;
-            i32x4 af[C::FM], bfr[C::FN];
 #pragma unroll
             for (int f = 0; f < C::FM; ++f)
-                af[f] = *reinterpret_cast<const i32x4 *>(
+                af[s][f] = *reinterpret_cast<const i32x4 *>(
                     As + swz(wm * C::TM + f * 32 + r, c));
 #pragma unroll
-            for (int f = 0; f < C::FN; ++f)
-                bfr[f] = *reinterpret_cast<const i32x4 *>(
-                    Bs + swz(wn * C::TN + f * 32 + r, c));
+            for (int f = 0; f < C::FN; ++f) {
+                if constexpr (C::B_KMAJOR)
+                    bfr[s][f] = read_b_kmajor<C>(Bs, kk, wn * C::TN + f * 32,
+                                                 lane);
+                else
+                    bfr[s][f] = *reinterpret_cast<const i32x4 *>(
+                        Bs + swz(wn * C::TN + f * 32 + r, c));
+            }
+        };
+        load(0, 0);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int s = kk & 1;
+            if (kk + 1 < 4) load(kk + 1, s ^ 1);
+            if constexpr (C::DTYPE == TG_BF16 && C::FM * C::FN >= 8) {
+                // interleave the next step's LDS reads with this step's
+                // MFMAs: one read after each of the first MFMAs
+                constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
+                if (kk + 1 < 4) {
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                    }
+                }
+            }
 #pragma unroll
             for (int i = 0; i < C::FM; ++i)
 #pragma unroll
                 for (int j = 0; j < C::FN; ++j) {
                     if constexpr (C::DTYPE == TG_BF16) {
-                        acc[i][j] = mfma_bf16(af[i], bfr[j], acc[i][j]);
+                        acc[i][j] = mfma_bf16(af[s][i], bfr[s][j], acc[i][j]);
                     } else {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            const uint32_t ua = af[i][e], ub = bfr[j][e];
+                            const uint32_t ua = af[s][i][e], ub = bfr[s][j][e];
                             acc[i][j] =
                                 mfma_f32(as_f32(ua), as_f32(ub), acc[i][j]);
                         }
@@ -256,116 +408,232 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
 // Store one program's accumulators into its own sub-tensor.
 // 32 x 32 MFMA result layout: lane l, register v holds
 //   row 8 * (v / 4) + 4 * (l / 32) + v % 4,  column l % 32.
+// Stores go through a buffer descriptor rooted at the sub-tensor's first
+// element with 32-bit offsets; elements outside the output (rows >= M,
+// columns >= N) get an out-of-range offset, which the hardware drops.
 template <class C>
-__device__ __forceinline__ void epilogue(const GemmArgs &g, int m0, int n0,
-                                         int wm, int wn, int lane,
+__device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
+                                         int lane,
                                          f32x16 (&acc)[C::FM][C::FN]) {
+    constexpr int OES = C::CBF16 ? 2 : 4;
     const int col_l = lane & 31, half = lane >> 5;
+    const int r0 = wm * C::TM + 4 * half;        // row of v = 0, i = 0
+    const int c0 = wn * C::TN + col_l;           // column of jj = 0
+    char *base = static_cast<char *>(j.c) +
+                 ((int64_t)j.m0 * j.ldc + j.n0) * OES;
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(
+        base, sat_bytes(((int64_t)(j.M - j.m0 - 1) * j.ldc + (j.N - j.n0)) *
+                        OES));
+    const int rows_left = j.M - j.m0 - r0;       // rows with local index < this
+    const int cols_left = j.N - j.n0 - c0;
+    float sb[C::FN];
 #pragma unroll
-    for (int j = 0; j < C::FN; ++j) {
-        const int col = n0 + wn * C::TN + j * 32 + col_l;
-        const bool col_ok = col < g.N;
-        const float sb = (g.scale_b && col_ok) ? g.scale_b[col] : 1.0f;
+    for (int jj = 0; jj < C::FN; ++jj)
+        sb[jj] = (j.scale_b && jj * 32 < cols_left) ? j.scale_b[j.n0 + c0 +
+                                                                jj * 32]
+                                                     : 1.0f;
+    const uint32_t lane_off = (uint32_t)((r0 * j.ldc + c0) * OES);
 #pragma unroll
-        for (int i = 0; i < C::FM; ++i) {
+    for (int i = 0; i < C::FM; ++i) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int row = m0 + wm * C::TM + i * 32 + 8 * (v >> 2) +
-                                4 * half + (v & 3);
-                if (col_ok && row < g.M) {
-                    float x = acc[i][j][v];
-                    if (g.scale_a) x *= g.scale_a[row];
-                    x *= sb;
-                    int64_t off = (int64_t)row * g.ldc + col;
-                    if constexpr (C::CBF16)
-                        static_cast<uint16_t *>(g.c)[off] = f32_to_bf16_bits(x);
-                    else
-                        static_cast<float *>(g.c)[off] = x;
-                    if (g.wcount)
-                        atomicAdd(&g.wcount[(int64_t)row * g.N + col], 1);
-                }
+        for (int v = 0; v < 16; ++v) {
+            const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
+            const bool row_ok = dr < rows_left;
+            const float sa =
+                (j.scale_a && row_ok) ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
+            const uint32_t roff = lane_off + (uint32_t)(dr * j.ldc * OES);
+#pragma unroll
+            for (int jj = 0; jj < C::FN; ++jj) {
+                const bool ok = row_ok && jj * 32 < cols_left;
+                const uint32_t off = ok ? roff + jj * 32 * OES : kOutOfRange;
+                const float x = acc[i][jj][v] * sb[jj] * sa;
+                if constexpr (C::CBF16)
+                    __builtin_amdgcn_raw_buffer_store_b16(
+                        (unsigned short)f32_to_bf16_bits(x), r, off, 0, 0);
+                else
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        __builtin_bit_cast(uint32_t, x), r, off, 0, 0);
             }
         }
     }
+    if (j.wcount) {
+        // instrumented launches: one count per stored element
+#pragma unroll 1
+        for (int i = 0; i < C::FM; ++i)
+#pragma unroll 1
+            for (int v = 0; v < 16; ++v) {
+                const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
+                if (dr >= rows_left) continue;
+#pragma unroll 1
+                for (int jj = 0; jj < C::FN; ++jj)
+                    if (jj * 32 < cols_left)
+                        atomicAdd(&j.wcount[(int64_t)(j.m0 + r0 + dr) * j.N +
+                                            j.n0 + c0 + jj * 32],
+                                  1);
+            }
+    }
 }
 
-// The body of one owned sub-tensor: zero accumulator, K loop, store.
 template <class C>
-__device__ __forceinline__ void run_tile(const GemmArgs &g, int tm, int tn,
-                                         char *smem) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wm = wave / C::WN, wn = wave % C::WN;
-    const int m0 = tm * C::BM, n0 = tn * C::BN;
-
-    f32x16 acc[C::FM][C::FN];
+__device__ __forceinline__ void zero_acc(f32x16 (&acc)[C::FM][C::FN]) {
 #pragma unroll
     for (int i = 0; i < C::FM; ++i)
 #pragma unroll
         for (int j = 0; j < C::FN; ++j)
 #pragma unroll
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-
-    const int nk_full = g.K / C::BK;
-    const int nk = nk_full + (g.K % C::BK != 0);
-    Tile<C> t;
-    if (nk > 0) {
-        if (nk_full > 0)
-            t.template load<false>(g, m0, n0, 0, tid);
-        else
-            t.template load<true>(g, m0, n0, 0, tid);
-        t.store(smem, tid);
-        __syncthreads();
-    }
-    for (int kt = 0; kt < nk; ++kt) {
-        const int nxt = kt + 1;
-        if (nxt < nk_full)
-            t.template load<false>(g, m0, n0, nxt * C::BK, tid);
-        else if (nxt < nk)
-            t.template load<true>(g, m0, n0, nxt * C::BK, tid);
-        compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc);
-        if (nxt < nk) t.store(smem + (nxt & 1) * C::STAGE, tid);
-        __syncthreads();
-    }
-    epilogue<C>(g, m0, n0, wm, wn, lane, acc);
 }
 
+// ------------------------------------------------------- persistent loops
+
+// Direct-load programs (bf16, e4m3).  P provides the owned sub-tensors:
+// P::n_prog(), P::count(), P::job(t).
+template <class C, class P>
+__device__ __forceinline__ void run_direct(const P &prov, char *smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    int t = program_slot(blockIdx.x, G);
+    if (t >= total) return;
+    Job j = prov.job(t);
+    if (j.K > 0) issue_direct<C>(j, smem, 0, wave, lane);  // stage 0
+    f32x16 acc[C::FM][C::FN];
+    while (true) {
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        wait_vmem();
+        __syncthreads();
+        zero_acc<C>(acc);
+        for (int kt = 0; kt < nk; ++kt) {
+            if (kt + 1 < nk)
+                issue_direct<C>(j, smem + ((kt + 1) & 1) * C::STAGE,
+                                (kt + 1) * C::BK, wave, lane);
+            compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc);
+            wait_vmem();
+            __syncthreads();
+        }
+        // fetch stage 0 of the next owned sub-tensor, then store this one
+        t += G;
+        const bool more = t < total;
+        Job nj;
+        if (more) {
+            nj = prov.job(t);
+            if (nj.K > 0) issue_direct<C>(nj, smem, 0, wave, lane);
+        }
+        epilogue<C>(j, wm, wn, lane, acc);
+        if (!more) break;
+        j = nj;
+    }
+}
+
+// Register-staged programs (f32).
+template <class C, class P>
+__device__ __forceinline__ void run_regs(const P &prov, char *smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    f32x16 acc[C::FM][C::FN];
+    for (int t = program_slot(blockIdx.x, G); t < total; t += G) {
+        const Job j = prov.job(t);
+        zero_acc<C>(acc);
+        const int nk_full = j.K / C::BK;
+        const int nk = nk_full + (j.K % C::BK != 0);
+        RegTile<C> rt;
+        if (nk > 0) {
+            if (nk_full > 0)
+                rt.template load<false>(j, 0, tid);
+            else
+                rt.template load<true>(j, 0, tid);
+            rt.store(smem, tid);
+            __syncthreads();
+        }
+        for (int kt = 0; kt < nk; ++kt) {
+            const int nxt = kt + 1;
+            if (nxt < nk_full)
+                rt.template load<false>(j, nxt * C::BK, tid);
+            else if (nxt < nk)
+                rt.template load<true>(j, nxt * C::BK, tid);
+            compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc);
+            if (nxt < nk) rt.store(smem + (nxt & 1) * C::STAGE, tid);
+            __syncthreads();
+        }
+        epilogue<C>(j, wm, wn, lane, acc);
+    }
+}
+
+// One problem: traversal index -> owned sub-tensor.
 template <class C>
-__global__ __launch_bounds__(C::THREADS) void gemm_tiled_kernel(GemmArgs g) {
-    extern __shared__ __align__(16) char smem[];
-    const int G = g.s.n_prog;
-    for (int t = program_slot(blockIdx.x, G); t < g.s.n_tiles; t += G) {
+struct SingleProvider {
+    const GemmArgs &g;
+    __device__ int n_prog() const { return g.s.n_prog; }
+    __device__ int count() const { return g.s.n_tiles; }
+    __device__ Job job(int t) const {
         int tm, tn;
         tile_coords(t, g.s, tm, tn);
-        run_tile<C>(g, tm, tn, smem);
+        Job j;
+        j.a = static_cast<const char *>(g.a);
+        j.b = static_cast<const char *>(g.b);
+        j.c = g.c;
+        j.scale_a = g.scale_a; j.scale_b = g.scale_b; j.wcount = g.wcount;
+        j.lda = g.lda; j.ldb = g.ldb; j.ldc = g.ldc;
+        j.M = g.M; j.N = g.N; j.K = g.K;
+        j.m0 = tm * C::BM; j.n0 = tn * C::BN;
+        return j;
     }
-}
+};
 
-// Grouped launch: programs walk the concatenated sub-tensor lists of all
-// problems of the table (binary search on the tile prefix sums).
+// Grouped launch: traversal index -> (problem, owned sub-tensor) by binary
+// search on the tile prefix sums of the problem table.
 template <class C>
-__global__ __launch_bounds__(C::THREADS) void gemm_grouped_kernel(
-    const GroupProblem *__restrict__ tab, int n, int total, int G) {
-    extern __shared__ __align__(16) char smem[];
-    for (int t = program_slot(blockIdx.x, G); t < total; t += G) {
+struct GroupProvider {
+    const GroupProblem *tab;
+    int n, total, G;
+    __device__ int n_prog() const { return G; }
+    __device__ int count() const { return total; }
+    __device__ Job job(int t) const {
         int lo = 0, hi = n - 1;
         while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
+            const int mid = (lo + hi + 1) >> 1;
             if (tab[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
         }
         const GroupProblem &pb = tab[lo];
-        GemmArgs g;
-        g.a = pb.a; g.b = pb.b; g.c = pb.c;
-        g.scale_a = nullptr; g.scale_b = nullptr; g.wcount = nullptr;
-        g.lda = pb.lda; g.ldb = pb.ldb; g.ldc = pb.ldc;
-        g.M = pb.M; g.N = pb.N; g.K = pb.K;
-        g.s.tiles_m = pb.tiles_m; g.s.tiles_n = pb.tiles_n;
-        g.s.n_tiles = pb.tiles_m * pb.tiles_n; g.s.n_prog = G;
-        g.s.group_m = 8;
+        Sched s;
+        s.tiles_m = pb.tiles_m; s.tiles_n = pb.tiles_n;
+        s.n_tiles = pb.tiles_m * pb.tiles_n; s.n_prog = G; s.group_m = 8;
         int tm, tn;
-        tile_coords(t - pb.tile_begin, g.s, tm, tn);
-        run_tile<C>(g, tm, tn, smem);
+        tile_coords(t - pb.tile_begin, s, tm, tn);
+        Job j;
+        j.a = static_cast<const char *>(pb.a);
+        j.b = static_cast<const char *>(pb.b);
+        j.c = pb.c;
+        j.scale_a = nullptr; j.scale_b = nullptr; j.wcount = nullptr;
+        j.lda = pb.lda; j.ldb = pb.ldb; j.ldc = pb.ldc;
+        j.M = pb.M; j.N = pb.N; j.K = pb.K;
+        j.m0 = tm * C::BM; j.n0 = tn * C::BN;
+        return j;
     }
+};
+
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void gemm_tiled_kernel(GemmArgs g) {
+    extern __shared__ __align__(1024) char smem[];
+    SingleProvider<C> p{g};
+    if constexpr (C::DIRECT)
+        run_direct<C>(p, smem);
+    else
+        run_regs<C>(p, smem);
+}
+
+template <class C>
+__global__ __launch_bounds__(C::THREADS) void gemm_grouped_kernel(
+    const GroupProblem *__restrict__ tab, int n, int total, int G) {
+    extern __shared__ __align__(1024) char smem[];
+    GroupProvider<C> p{tab, n, total, G};
+    if constexpr (C::DIRECT)
+        run_direct<C>(p, smem);
+    else
+        run_regs<C>(p, smem);
 }
 
 struct VariantEntry {

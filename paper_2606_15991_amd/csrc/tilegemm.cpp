@@ -206,7 +206,8 @@ tg_status describe(const tg_in *A, const tg_in *B, const tg_out *C,
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Can the tiled kernel take this operand layout?
-bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B, int dt) {
+bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B,
+              const tg_out *C, int dt) {
     int es = esize(dt);
     int epc = 16 / es;
     if (p.a_dt != p.b_dt) return false;
@@ -215,6 +216,11 @@ bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B, int dt) {
     if ((A->ld * es) % 16 || (B->ld * es) % 16) return false;
     if (p.K % epc) return false;
     if (!p.b_nk && (p.N % epc)) return false;
+    // the kernels address a sub-tensor with 32-bit byte offsets: 256 rows of
+    // any operand (and of C in binary32) must span less than 2^31 bytes
+    const int64_t lim = (int64_t)1 << 31;
+    if (A->ld * es * 256 >= lim || B->ld * es * 256 >= lim) return false;
+    if (C->ld * 4 * 256 >= lim) return false;
     return true;
 }
 
@@ -291,8 +297,10 @@ tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
     }
     // split precisions run the tiled bf16 kernel on the plane operands,
     // whose layout the library lays out itself (always aligned)
-    bool t_ok = np > 1 ? ((p.K * np) % 8 == 0 && (p.b_nk || p.N % 8 == 0))
-                       : tiled_ok(p, A, B, p.a_dt);
+    bool t_ok = np > 1 ? ((p.K * np) % 8 == 0 && (p.b_nk || p.N % 8 == 0) &&
+                          p.K * np * 2 * 256 < ((int64_t)1 << 31) &&
+                          C->ld * 4 * 256 < ((int64_t)1 << 31))
+                       : tiled_ok(p, A, B, C, p.a_dt);
     bool s_ok = np == 1 && skinny_ok(p, A, B);
     if (cfg.kind == TG_KIND_AUTO) {
         if (s_ok && (cfg.bm == 0 || (cfg.bm >= p.M && cfg.bm <= 16)) &&
@@ -639,7 +647,7 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
         }
         if (ps[i].a_dt != TG_BF16 || ps[i].b_dt != TG_BF16)
             return fail(TG_E_DTYPE, "problem %d: grouped launch is bf16", i);
-        if (!tiled_ok(ps[i], &A[i], &B[i], TG_BF16))
+        if (!tiled_ok(ps[i], &A[i], &B[i], &C[i], TG_BF16))
             return fail(TG_E_UNSUPPORTED, "problem %d: layout not tileable",
                         i);
         if (c_bf16 < 0) c_bf16 = ps[i].c_bf16;
