@@ -242,6 +242,101 @@ tg_status tile_gemm_grouped(void *workspace, tg_stream stream);
 tg_status tile_error_norm(const void *C, int32_t c_dtype, const double *R,
                           int64_t n, double *out, tg_stream stream);
 
+/* ------------------------------------------------------------------------
+ * Configuration choice.  The tile shapes of the paper's evaluation are tuned
+ * once per problem size (Sec. 5.1); here an exhaustive autotuner times every
+ * candidate configuration, a cache keeps the winners, and a learned cost
+ * model (an MLP trained on the autotuner's timings by the kernels below)
+ * picks configurations for shapes that were never tuned.  tile_gemm with no
+ * configuration and no partition uses, in order: the tuning cache, the
+ * picker's argmin over tile_gemm_candidates, the fixed default heuristic
+ * (tile_picker_mode selects which of the first two are enabled).
+ * ---------------------------------------------------------------------- */
+
+/*
+ * tile_gemm_candidates -- every configuration tile_gemm accepts for these
+ * arguments (honouring C's partition when it is set).  Writes up to `max`
+ * into `out` (host) and returns the total count, or -1 on invalid arguments.
+ * Host only.
+ */
+int32_t tile_gemm_candidates(const tg_in *A, const tg_in *B, const tg_out *C,
+                             const tg_opts *opts, tg_config *out, int32_t max);
+
+typedef struct tg_tune_result {
+    tg_config cfg;
+    float ms;             /* average launch time, or -1 when it failed       */
+    int32_t status;       /* tg_status of the launches                       */
+} tg_tune_result;
+
+/*
+ * tile_autotune -- run every candidate once (warm-up) then `reps` times on
+ * `stream`, timed with HIP events, and record the fastest in the tuning
+ * cache.  C is written (any candidate's result).  results (host, up to
+ * max_results entries) and best (host) may be NULL.  Synchronises the
+ * stream: not capturable.
+ */
+tg_status tile_autotune(const tg_in *A, const tg_in *B, tg_out *C,
+                        const tg_opts *opts, int32_t reps,
+                        tg_tune_result *results, int32_t max_results,
+                        int32_t *n_results, tg_config *best, tg_stream stream);
+
+/* Tuning cache: clear, count, save to / merge from a text file (host). */
+tg_status tile_tune_cache_clear(void);
+int32_t tile_tune_cache_size(void);
+tg_status tile_tune_cache_save(const char *path);
+tg_status tile_tune_cache_load(const char *path);
+
+/*
+ * Picker.  TG_PICKER_FEATURES numbers describe a (request, configuration)
+ * pair: log2 M, N, K; e4m3 / f32 operand flags; B stored N x K; kernel kind
+ * (three one-hot flags); log2 bm, bn, ksplit; log2 of the sub-tensor count
+ * and of the sub-tensors per program; useful fraction of the padded output
+ * area; log2 of 2MNK.  tile_picker_set installs a cost model (host copy of
+ * the parameters in the layout of tile_mlp_*, with per-feature mean and
+ * standard deviation used to normalise the features); params == NULL
+ * removes it.  tile_picker_mode(mode) sets bit 1 = use the tuning cache,
+ * bit 2 = use the cost model (mode < 0 only queries) and returns the
+ * previous mode.
+ */
+#define TG_PICKER_FEATURES 16
+tg_status tile_picker_features(const tg_in *A, const tg_in *B,
+                               const tg_out *C, const tg_config *cfg,
+                               float *feat);
+tg_status tile_picker_set(const float *params, int32_t n_in, int32_t hidden,
+                          int32_t depth, const float *feat_mean,
+                          const float *feat_std);
+tg_status tile_picker_predict(const float *feat, float *log_ms);
+int32_t tile_picker_mode(int32_t mode);
+
+/*
+ * Cost-model MLP on the GPU: `depth` hidden ReLU layers of `hidden` units and
+ * one linear output.  Parameters (device, binary32), per layer: W (out x in,
+ * row-major) then b (out); the output layer has out = 1.  X is batch x n_in
+ * row-major (device), y and out are batch values (device).
+ *   tile_mlp_forward:   out = MLP(X)
+ *   tile_mlp_loss_grad: loss (device, 1 value) = mean (MLP(X) - y)^2 and
+ *                       grads (device, same layout as params) = dloss/dparams
+ *   tile_mlp_adam:      one Adam step (Kingma & Ba) at step t >= 1 on n
+ *                       parameters with moment buffers m, v (device)
+ * ws (device) holds activations: tile_mlp_workspace_bytes bytes.  All
+ * reductions run in a fixed order: repeated calls give identical results.
+ */
+size_t tile_mlp_param_count(int32_t n_in, int32_t hidden, int32_t depth);
+size_t tile_mlp_workspace_bytes(int32_t n_in, int32_t hidden, int32_t depth,
+                                int32_t batch);
+tg_status tile_mlp_forward(const float *params, int32_t n_in, int32_t hidden,
+                           int32_t depth, const float *X, int32_t batch,
+                           float *out, void *ws, size_t ws_bytes,
+                           tg_stream stream);
+tg_status tile_mlp_loss_grad(const float *params, int32_t n_in,
+                             int32_t hidden, int32_t depth, const float *X,
+                             const float *y, int32_t batch, float *grads,
+                             float *loss, void *ws, size_t ws_bytes,
+                             tg_stream stream);
+tg_status tile_mlp_adam(float *params, const float *grads, float *m, float *v,
+                        int64_t n, float lr, float beta1, float beta2,
+                        float eps, int32_t t, tg_stream stream);
+
 const char *tg_status_str(int32_t status);
 const char *tg_last_error(void);
 

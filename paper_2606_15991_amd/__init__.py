@@ -72,6 +72,14 @@ class tg_opts(ctypes.Structure):
                 ("write_count", ctypes.c_void_p)]
 
 
+class tg_tune_result(ctypes.Structure):
+    _fields_ = [("cfg", tg_config), ("ms", ctypes.c_float),
+                ("status", ctypes.c_int32)]
+
+
+TG_PICKER_FEATURES = 16
+
+
 class TileGemmError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{status_str(status)}: {message}")
@@ -112,6 +120,41 @@ def _load():
     lib.tg_last_error.restype = ctypes.c_char_p
     lib.tg_device_cus.argtypes = []
     lib.tg_device_cus.restype = i32
+    fp = P(ctypes.c_float)
+    vp = ctypes.c_void_p
+    lib.tile_gemm_candidates.argtypes = [P(tg_in), P(tg_in), P(tg_out),
+                                         P(tg_opts), P(tg_config), i32]
+    lib.tile_gemm_candidates.restype = i32
+    lib.tile_autotune.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
+                                  i32, P(tg_tune_result), i32, P(i32),
+                                  P(tg_config), vp]
+    lib.tile_tune_cache_clear.argtypes = []
+    lib.tile_tune_cache_size.argtypes = []
+    lib.tile_tune_cache_size.restype = i32
+    lib.tile_tune_cache_save.argtypes = [ctypes.c_char_p]
+    lib.tile_tune_cache_load.argtypes = [ctypes.c_char_p]
+    lib.tile_picker_features.argtypes = [P(tg_in), P(tg_in), P(tg_out),
+                                         P(tg_config), fp]
+    lib.tile_picker_set.argtypes = [fp, i32, i32, i32, fp, fp]
+    lib.tile_picker_predict.argtypes = [fp, fp]
+    lib.tile_picker_mode.argtypes = [i32]
+    lib.tile_picker_mode.restype = i32
+    lib.tile_mlp_param_count.argtypes = [i32, i32, i32]
+    lib.tile_mlp_param_count.restype = ctypes.c_size_t
+    lib.tile_mlp_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.tile_mlp_workspace_bytes.restype = ctypes.c_size_t
+    lib.tile_mlp_forward.argtypes = [vp, i32, i32, i32, vp, i32, vp, vp,
+                                     ctypes.c_size_t, vp]
+    lib.tile_mlp_loss_grad.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp,
+                                       vp, vp, ctypes.c_size_t, vp]
+    lib.tile_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64,
+                                  ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, ctypes.c_float, i32, vp]
+    for f in ("tile_autotune", "tile_tune_cache_clear", "tile_tune_cache_save",
+              "tile_tune_cache_load", "tile_picker_features",
+              "tile_picker_set", "tile_picker_predict", "tile_mlp_forward",
+              "tile_mlp_loss_grad", "tile_mlp_adam"):
+        getattr(lib, f).restype = i32
     for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
               "tile_gemm_grouped_prepare", "tile_gemm_grouped",
               "tile_error_norm"):
@@ -327,3 +370,140 @@ def tile_error_norm(C, R, out=None, stream=None):
 
 def device_cus() -> int:
     return int(lib.tg_device_cus())
+
+
+# ------------------------------------------------------------ configuration
+
+def tile_gemm_candidates(A, B, C, bm=0, bn=0, *, b_trans=False,
+                         precision="native"):
+    """Configurations tile_gemm accepts for these arguments (dicts)."""
+    buf = (tg_config * 64)()
+    n = lib.tile_gemm_candidates(make_in(A), make_in(B, b_trans),
+                                 make_out(C, bm, bn), make_opts(precision),
+                                 buf, 64)
+    if n < 0:
+        raise TileGemmError(TG_E_ARG, last_error())
+    return [buf[i].as_dict() for i in range(min(n, 64))]
+
+
+def tile_autotune(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
+                  scale_a=None, scale_b=None, workspace=None, reps=3,
+                  stream=None):
+    """Time every candidate; returns (best config dict, [(cfg, ms, status)]).
+    The winner is recorded in the library's tuning cache."""
+    res = (tg_tune_result * 64)()
+    nres = ctypes.c_int32(0)
+    best = tg_config()
+    o = make_opts(precision, scale_a, scale_b, None, workspace)
+    if o.precision != TG_PREC_NATIVE and workspace is None:
+        need = lib.tile_gemm_workspace_size(make_in(A), make_in(B, b_trans),
+                                            make_out(C, bm, bn), o)
+        workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = need
+    st = lib.tile_autotune(make_in(A), make_in(B, b_trans),
+                           make_out(C, bm, bn), o, int(reps), res, 64,
+                           ctypes.byref(nres), ctypes.byref(best),
+                           _stream(stream))
+    _raise(st)
+    rows = [(res[i].cfg.as_dict(), float(res[i].ms), int(res[i].status))
+            for i in range(nres.value)]
+    return best.as_dict(), rows
+
+
+def tile_tune_cache_clear():
+    _raise(lib.tile_tune_cache_clear())
+
+
+def tile_tune_cache_size() -> int:
+    return int(lib.tile_tune_cache_size())
+
+
+def tile_tune_cache_save(path):
+    _raise(lib.tile_tune_cache_save(str(path).encode()))
+
+
+def tile_tune_cache_load(path):
+    _raise(lib.tile_tune_cache_load(str(path).encode()))
+
+
+def tile_picker_features(A, B, C, config, bm=0, bn=0, *, b_trans=False):
+    f = (ctypes.c_float * TG_PICKER_FEATURES)()
+    c = make_config(config)
+    _raise(lib.tile_picker_features(make_in(A), make_in(B, b_trans),
+                                    make_out(C, bm, bn), c, f))
+    return list(f)
+
+
+def _fbuf(vals):
+    return (ctypes.c_float * len(vals))(*[float(v) for v in vals])
+
+
+def tile_picker_set(params, n_in, hidden, depth, mean, std):
+    """Install a cost model (host copy); params=None removes it."""
+    if params is None:
+        _raise(lib.tile_picker_set(None, 0, 0, 0, None, None))
+        return
+    p = [float(x) for x in params]
+    _raise(lib.tile_picker_set(_fbuf(p), n_in, hidden, depth, _fbuf(mean),
+                               _fbuf(std)))
+
+
+def tile_picker_predict(feat) -> float:
+    out = ctypes.c_float(0)
+    _raise(lib.tile_picker_predict(_fbuf(feat), ctypes.byref(out)))
+    return float(out.value)
+
+
+def tile_picker_mode(mode=-1) -> int:
+    return int(lib.tile_picker_mode(int(mode)))
+
+
+def tile_mlp_param_count(n_in, hidden, depth) -> int:
+    return int(lib.tile_mlp_param_count(n_in, hidden, depth))
+
+
+def tile_mlp_workspace_bytes(n_in, hidden, depth, batch) -> int:
+    return int(lib.tile_mlp_workspace_bytes(n_in, hidden, depth, batch))
+
+
+def _mlp_ws(n_in, hidden, depth, batch, device, ws):
+    need = tile_mlp_workspace_bytes(n_in, hidden, depth, batch)
+    if ws is None or ws.numel() * ws.element_size() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    return ws, need
+
+
+def tile_mlp_forward(params, X, n_in, hidden, depth, out=None, ws=None,
+                     stream=None):
+    batch = X.shape[0]
+    if out is None:
+        out = torch.empty(batch, dtype=torch.float32, device=X.device)
+    ws, need = _mlp_ws(n_in, hidden, depth, batch, X.device, ws)
+    _raise(lib.tile_mlp_forward(params.data_ptr(), n_in, hidden, depth,
+                                X.data_ptr(), batch, out.data_ptr(),
+                                ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out
+
+
+def tile_mlp_loss_grad(params, X, y, n_in, hidden, depth, grads=None,
+                       loss=None, ws=None, stream=None):
+    batch = X.shape[0]
+    if grads is None:
+        grads = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    ws, need = _mlp_ws(n_in, hidden, depth, batch, X.device, ws)
+    _raise(lib.tile_mlp_loss_grad(params.data_ptr(), n_in, hidden, depth,
+                                  X.data_ptr(), y.data_ptr(), batch,
+                                  grads.data_ptr(), loss.data_ptr(),
+                                  ws.data_ptr(), ws.numel(), _stream(stream)))
+    return loss, grads
+
+
+def tile_mlp_adam(params, grads, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999,
+                  eps=1e-8, stream=None):
+    _raise(lib.tile_mlp_adam(params.data_ptr(), grads.data_ptr(),
+                             m.data_ptr(), v.data_ptr(), params.numel(),
+                             lr, beta1, beta2, eps, int(t), _stream(stream)))
+    return params

@@ -21,6 +21,25 @@ namespace {
 
 constexpr int UNROLL = 4;
 
+// 16 bytes at p of which only the first n (0..16) are inside the operand;
+// the rest read as zero.  Used for the one chunk per row that straddles K.
+__device__ __forceinline__ uint4 ld16_head(const char *p, int n) {
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+        if (b < n) w[b >> 2] |= (uint32_t)(uint8_t)p[b] << (8 * (b & 3));
+    return uint4{w[0], w[1], w[2], w[3]};
+}
+
+// Chunk of `epc` elements of `es` bytes starting at element k of a row of
+// `K` elements: whole, partial, or past the end.
+__device__ __forceinline__ uint4 ld_chunk(const char *row, int k, int K,
+                                          int epc, int es) {
+    if (k + epc <= K) return ld16(row + (int64_t)k * es);
+    if (k < K) return ld16_head(row + (int64_t)k * es, (K - k) * es);
+    return uint4{0, 0, 0, 0};
+}
+
 template <int WDT, int KS, bool CBF16>
 __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     // Elements of K covered by one 16-byte weight load per lane group:
@@ -46,26 +65,29 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     const int nsteps = (g.K + KSTEP - 1) / KSTEP;
     // wave w takes super-steps w, w + KS, ... of UNROLL K steps each
     for (int s0 = wave * UNROLL; s0 < nsteps; s0 += KS * UNROLL) {
+        constexpr int WES = WDT == TG_BF16 ? 2 : 1;
         uint4 wv[UNROLL];
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            int k = (s0 + u) * KSTEP + grp * EPL;
-            if (s0 + u < nsteps && k < g.K)
-                wv[u] = ld16(W + (int64_t)k * (WDT == TG_BF16 ? 2 : 1));
-            else
-                wv[u] = uint4{0, 0, 0, 0};
+            const int k = (s0 + u) * KSTEP + grp * EPL;
+            wv[u] = s0 + u < nsteps ? ld_chunk(W, k, g.K, EPL, WES)
+                                    : uint4{0, 0, 0, 0};
         }
+        const char *Xc = reinterpret_cast<const char *>(X);
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
-            int k = (s0 + u) * KSTEP + grp * EPL;
-            bool ok = xrow_ok && s0 + u < nsteps && k < g.K;
+            const int k = (s0 + u) * KSTEP + grp * EPL;
+            const bool ok = xrow_ok && s0 + u < nsteps && k < g.K;
             if constexpr (WDT == TG_BF16) {
-                uint4 xv = ok ? ld16(X + k) : uint4{0, 0, 0, 0};
+                const uint4 xv = ok ? ld_chunk(Xc, k, g.K, 8, 2)
+                                    : uint4{0, 0, 0, 0};
                 acc = mfma16_bf16(__builtin_bit_cast(i32x4, wv[u]),
                                   __builtin_bit_cast(i32x4, xv), acc);
             } else {
-                uint4 x0 = ok ? ld16(X + k) : uint4{0, 0, 0, 0};
-                uint4 x1 = ok ? ld16(X + k + 8) : uint4{0, 0, 0, 0};
+                const uint4 x0 = ok ? ld_chunk(Xc, k, g.K, 8, 2)
+                                    : uint4{0, 0, 0, 0};
+                const uint4 x1 = ok ? ld_chunk(Xc, k + 8, g.K, 8, 2)
+                                    : uint4{0, 0, 0, 0};
                 uint2 w01 = e4m3x4_to_bf16x4(wv[u].x);
                 uint2 w23 = e4m3x4_to_bf16x4(wv[u].y);
                 uint2 w45 = e4m3x4_to_bf16x4(wv[u].z);

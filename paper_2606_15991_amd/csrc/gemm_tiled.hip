@@ -9,9 +9,8 @@
 // gfx950 design:
 //   * every K tile is 128 bytes deep (64 bf16, 32 f32 or 128 e4m3);
 //   * k-contiguous operands (A, and B stored N x K) live in LDS as
-//     [rows][128 B] with the 16-byte chunk index XOR-swizzled by (row & 7),
-//     so the 16-byte fragment reads of 8 consecutive rows hit 8 distinct
-//     chunk positions;
+//     [rows][128 B] with the 16-byte chunk index XOR-swizzled per row so
+//     that the 16-byte fragment reads are free of bank conflicts;
 //   * bf16 and e4m3 tiles move from HBM to LDS with direct buffer->LDS
 //     loads (no staging registers, no LDS write instructions): lane l of a
 //     wavefront writes LDS bytes [16 l, 16 l + 16) of a 1 KiB block, so each
@@ -19,7 +18,7 @@
 //     position; one buffer descriptor per operand and K tile, offsets past
 //     its end (rows beyond M or N, K beyond the tail) load zeros;
 //   * a bf16 B stored K x N stays k-major in LDS ([BK][BN], chunk index
-//     XOR-swizzled by 2 (k & 3)) and is read with the transposing LDS read,
+//     XOR-swizzled by k & 3) and is read with the transposing LDS read,
 //     which hands each lane four consecutive k of one column;
 //   * two LDS stages: the next K tile streams into stage s ^ 1 while the
 //     MFMAs consume stage s; one barrier per K tile; the first stage of the
@@ -86,15 +85,29 @@ struct Cfg {
     static_assert(!B_KMAJOR || CPR >= 4, "k-major B rows of >= 64 bytes");
 };
 
+// Row-major [rows][128 B] operand stage: chunk c of row r sits at chunk
+// position c ^ f(r), f(r) = (r ^ (r >> 3)) & 7.  Any 16 consecutive rows
+// read at one logical chunk then cover 16 distinct 16-byte bank groups of a
+// 256-byte bank window (and any 8 of them 8 groups of a 128-byte window), so
+// the 16-byte fragment reads are conflict-free.
+__device__ __forceinline__ int swz_f(int row) { return (row ^ (row >> 3)) & 7; }
 __device__ __forceinline__ int swz(int row, int chunk) {
-    return row * 128 + ((chunk ^ (row & 7)) << 4);
+    return row * 128 + ((chunk ^ swz_f(row)) << 4);
 }
 
-// Chunk permutation of k-major B rows: rows k .. k+3 of a 16-lane
-// transposing read land in four distinct 32-byte bank groups.
+// Chunk permutation of k-major B rows, by k & 3: the four rows of a 16-lane
+// transposing read (and of two such groups read together) land in distinct
+// 16-byte bank groups.
 template <class C>
 __device__ __forceinline__ int swz_kmajor(int k) {
-    return (2 * (k & 3)) & (C::CPR - 1);
+    if constexpr (C::CPR >= 16) {
+        constexpr uint32_t tab = 0u | (4u << 8) | (10u << 16) | (14u << 24);
+        return (tab >> (8 * (k & 3))) & 0xff;
+    } else if constexpr (C::CPR == 8) {
+        return 2 * (k & 3);
+    } else {
+        return 2 * (k & 1);
+    }
 }
 
 __device__ __forceinline__ void wait_vmem() {
@@ -145,22 +158,27 @@ __device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
 template <class C>
 __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
                                              int k0, int wave, int lane) {
+    // lane l of the 1 KiB block of rows 8 rb .. 8 rb + 7 writes row
+    // 8 rb + l / 8 at chunk position l % 8, which holds logical chunk
+    // (l % 8) ^ f(row) = (l % 8) ^ (l / 8) ^ (rb % 8)
     const int rsub = lane >> 3;
-    const int kc = (lane & 7) ^ rsub;
-    const bool kin = k0 + kc * C::EPC < j.K;
+    const int kc0 = (lane & 7) ^ rsub;
     {
         // A rows m0.. : descriptor from (m0, k0); rows >= M are past its end
         const char *base = j.a + ((int64_t)j.m0 * j.lda + k0) * C::ES;
         const uint32_t nrec =
             sat_bytes(((int64_t)(j.M - j.m0) * j.lda - k0) * C::ES);
         const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
-        const uint32_t off0 =
-            (uint32_t)(((wave * 8 + rsub) * j.lda + kc * C::EPC) * C::ES);
+        const uint32_t off0 = (uint32_t)((wave * 8 + rsub) * j.lda * C::ES);
         const uint32_t step = (uint32_t)(C::NW * 8 * j.lda * C::ES);
 #pragma unroll
-        for (int i = 0; i < C::BM / 8 / C::NW; ++i)
-            buf_to_lds(r, stage + (i * C::NW + wave) * 1024,
-                       kin ? off0 + i * step : kOutOfRange);
+        for (int i = 0; i < C::BM / 8 / C::NW; ++i) {
+            const int rb = i * C::NW + wave;
+            const int kc = kc0 ^ (rb & 7);
+            const bool kin = k0 + (kc + 1) * C::EPC <= j.K;
+            buf_to_lds(r, stage + rb * 1024,
+                       kin ? off0 + i * step + kc * 16 : kOutOfRange);
+        }
     }
     char *Bs = stage + C::BM * 128;
     if constexpr (!C::B_KMAJOR) {
@@ -168,13 +186,16 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
         const uint32_t nrec =
             sat_bytes(((int64_t)(j.N - j.n0) * j.ldb - k0) * C::ES);
         const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
-        const uint32_t off0 =
-            (uint32_t)(((wave * 8 + rsub) * j.ldb + kc * C::EPC) * C::ES);
+        const uint32_t off0 = (uint32_t)((wave * 8 + rsub) * j.ldb * C::ES);
         const uint32_t step = (uint32_t)(C::NW * 8 * j.ldb * C::ES);
 #pragma unroll
-        for (int i = 0; i < C::BN / 8 / C::NW; ++i)
-            buf_to_lds(r, Bs + (i * C::NW + wave) * 1024,
-                       kin ? off0 + i * step : kOutOfRange);
+        for (int i = 0; i < C::BN / 8 / C::NW; ++i) {
+            const int rb = i * C::NW + wave;
+            const int kc = kc0 ^ (rb & 7);
+            const bool kin = k0 + (kc + 1) * C::EPC <= j.K;
+            buf_to_lds(r, Bs + rb * 1024,
+                       kin ? off0 + i * step + kc * 16 : kOutOfRange);
+        }
     } else {
         // k-major B: descriptor from (k0, n0); rows k >= K are past its end,
         // columns >= N are masked per lane
@@ -484,6 +505,49 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[C::FM][C::FN]) {
             for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
 }
 
+// K not a multiple of the 16-byte chunk: the chunk that straddles K was
+// loaded as zeros; write its K % EPC valid elements of every row (A, and B
+// stored N x K) into LDS one by one.  Called after the stage's loads have
+// landed and all wavefronts passed a barrier; a barrier must follow.
+template <class C>
+__device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
+                                            int tid) {
+    const int rem = j.K % C::EPC;
+    const int kbase = j.K - rem;                  // first element of the chunk
+    const int chunk = (kbase - k0) / C::EPC;      // its logical chunk index
+    for (int r = tid; r < C::BM; r += C::THREADS) {
+        const int row = j.m0 + r;
+        char *dst = stage + swz(r, chunk);
+        const char *src = j.a + ((int64_t)row * j.lda + kbase) * C::ES;
+        for (int e = 0; e < rem; ++e) {
+            if constexpr (C::ES == 2)
+                reinterpret_cast<uint16_t *>(dst)[e] =
+                    row < j.M ? reinterpret_cast<const uint16_t *>(src)[e] : 0;
+            else
+                reinterpret_cast<uint8_t *>(dst)[e] =
+                    row < j.M ? reinterpret_cast<const uint8_t *>(src)[e] : 0;
+        }
+    }
+    if constexpr (!C::B_KMAJOR) {
+        char *Bs = stage + C::BM * 128;
+        for (int r = tid; r < C::BN; r += C::THREADS) {
+            const int row = j.n0 + r;
+            char *dst = Bs + swz(r, chunk);
+            const char *src = j.b + ((int64_t)row * j.ldb + kbase) * C::ES;
+            for (int e = 0; e < rem; ++e) {
+                if constexpr (C::ES == 2)
+                    reinterpret_cast<uint16_t *>(dst)[e] =
+                        row < j.N ? reinterpret_cast<const uint16_t *>(src)[e]
+                                  : 0;
+                else
+                    reinterpret_cast<uint8_t *>(dst)[e] =
+                        row < j.N ? reinterpret_cast<const uint8_t *>(src)[e]
+                                  : 0;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------- persistent loops
 
 // Direct-load programs (bf16, e4m3).  P provides the owned sub-tensors:
@@ -501,8 +565,14 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
     f32x16 acc[C::FM][C::FN];
     while (true) {
         const int nk = (j.K + C::BK - 1) / C::BK;
+        // the last K tile holds a chunk that straddles K
+        const bool ragged = (j.K % C::EPC) != 0;
         wait_vmem();
         __syncthreads();
+        if (ragged && nk == 1) {
+            fill_k_tail<C>(j, smem, 0, tid);
+            __syncthreads();
+        }
         zero_acc<C>(acc);
         for (int kt = 0; kt < nk; ++kt) {
             if (kt + 1 < nk)
@@ -511,6 +581,11 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
             compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc);
             wait_vmem();
             __syncthreads();
+            if (ragged && kt + 2 == nk) {
+                fill_k_tail<C>(j, smem + ((kt + 1) & 1) * C::STAGE,
+                               (kt + 1) * C::BK, tid);
+                __syncthreads();
+            }
         }
         // fetch stage 0 of the next owned sub-tensor, then store this one
         t += G;

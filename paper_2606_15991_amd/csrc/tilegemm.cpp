@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "host_internal.hpp"
 #include "tg_internal.hpp"
 
 using namespace tg;
@@ -214,7 +216,9 @@ bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B,
     if (dt == TG_FP8_E4M3 && !p.b_nk) return false;
     if (!aligned16(A->data) || !aligned16(B->data)) return false;
     if ((A->ld * es) % 16 || (B->ld * es) % 16) return false;
-    if (p.K % epc) return false;
+    // bf16 / e4m3 take any K (the straddling chunk is filled element-wise);
+    // the f32 register path needs whole 16-byte chunks
+    if (dt == TG_F32 && p.K % epc) return false;
     if (!p.b_nk && (p.N % epc)) return false;
     // the kernels address a sub-tensor with 32-bit byte offsets: 256 rows of
     // any operand (and of C in binary32) must span less than 2^31 bytes
@@ -227,8 +231,6 @@ bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B,
 bool skinny_ok(const Problem &p, const tg_in *A, const tg_in *B) {
     if (p.M > 16 || !p.b_nk || p.a_dt != TG_BF16) return false;
     if (p.b_dt != TG_BF16 && p.b_dt != TG_FP8_E4M3) return false;
-    int epl = p.b_dt == TG_BF16 ? 8 : 16;
-    if (p.K % epl) return false;
     if (!aligned16(A->data) || !aligned16(B->data)) return false;
     if ((A->ld * 2) % 16 || (B->ld * esize(p.b_dt)) % 16) return false;
     return true;
@@ -270,9 +272,8 @@ struct Launch {
     Sched s;
 };
 
-tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
-                 const tg_out *C, const tg_opts *o, Launch &L) {
-    const tg_config *uc = o ? o->config : nullptr;
+tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
+                          const tg_out *C, const tg_config *uc, Launch &L) {
     tg_config cfg{};
     if (uc) cfg = *uc;
     if (cfg.kind < TG_KIND_AUTO || cfg.kind > TG_KIND_SIMPLE)
@@ -397,6 +398,112 @@ tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
     }
     L.cfg = cfg;
     return TG_OK;
+}
+
+host::Key key_of(const Problem &p) {
+    host::Key k;
+    k.M = p.M; k.N = p.N; k.K = p.K;
+    k.a_dt = p.a_dt; k.b_dt = p.b_dt; k.b_nk = p.b_nk; k.c_bf16 = p.c_bf16;
+    k.precision = p.precision;
+    return k;
+}
+
+// Every configuration tile_gemm can run for this request.
+void candidates(const Problem &p, const tg_in *A, const tg_in *B,
+                const tg_out *C, std::vector<tg_config> &out) {
+    out.clear();
+    auto try_cfg = [&](const tg_config &c) {
+        Launch L;
+        std::string keep = g_err;
+        if (choose_explicit(p, A, B, C, &c, L) == TG_OK) out.push_back(L.cfg);
+        g_err = keep;
+    };
+    const int np = p.precision == TG_PREC_BF16X3 ? 3
+                   : p.precision == TG_PREC_BF16X6 ? 6 : 1;
+    const int gdt = np > 1 ? TG_BF16 : p.a_dt;
+    for (int ks : {1, 2, 4, 8, 16}) {
+        tg_config c{};
+        c.kind = TG_KIND_SKINNY;
+        c.ksplit = ks;
+        try_cfg(c);
+    }
+    const int n = tiled_variant_count();
+    for (int i = 0; i < n; ++i) {
+        const TiledVariant &v = tiled_variant(i);
+        if (v.dtype != gdt || v.b_nk != (int)p.b_nk || v.c_bf16 != (int)p.c_bf16)
+            continue;
+        tg_config c{};
+        c.kind = TG_KIND_TILED;
+        c.bm = v.bm; c.bn = v.bn; c.wm = v.wm; c.wn = v.wn;
+        try_cfg(c);
+    }
+    // the element-wise fallback competes only where nothing else runs
+    if (!out.empty()) return;
+    for (int t : {64, 32}) {
+        tg_config c{};
+        c.kind = TG_KIND_SIMPLE;
+        c.bm = c.bn = t;
+        try_cfg(c);
+    }
+}
+
+float lg2(double x) { return (float)std::log2(x < 1.0 ? 1.0 : x); }
+
+// Picker features of one (request, configuration) pair.
+void features(const Problem &p, const Launch &L, float *f) {
+    const tg_config &c = L.cfg;
+    const double tiles = L.s.n_tiles > 0 ? L.s.n_tiles : 1;
+    const double progs = L.s.n_prog > 0 ? L.s.n_prog : 1;
+    f[0] = lg2((double)p.M);
+    f[1] = lg2((double)p.N);
+    f[2] = lg2((double)p.K);
+    f[3] = (p.a_dt == TG_FP8_E4M3 || p.b_dt == TG_FP8_E4M3) ? 1.f : 0.f;
+    f[4] = p.a_dt == TG_F32 ? 1.f : 0.f;
+    f[5] = p.b_nk ? 1.f : 0.f;
+    f[6] = c.kind == TG_KIND_TILED ? 1.f : 0.f;
+    f[7] = c.kind == TG_KIND_SKINNY ? 1.f : 0.f;
+    f[8] = c.kind == TG_KIND_SIMPLE ? 1.f : 0.f;
+    f[9] = lg2((double)c.bm);
+    f[10] = lg2((double)c.bn);
+    f[11] = lg2((double)(c.ksplit > 0 ? c.ksplit : 1));
+    f[12] = lg2(tiles);
+    f[13] = lg2(std::ceil(tiles / progs));
+    f[14] = (float)((double)p.M * (double)p.N /
+                    (tiles * (double)c.bm * (double)c.bn));
+    f[15] = lg2(2.0 * (double)p.M * (double)p.N * (double)(p.K > 0 ? p.K : 1));
+}
+
+// Configuration when the caller gives none: the tuning cache, then the
+// learned picker's argmin over the candidates, then the fixed heuristic.
+tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
+                 const tg_out *C, const tg_opts *o, Launch &L) {
+    const tg_config *uc = o ? o->config : nullptr;
+    if (uc || C->bm > 0 || C->bn > 0)
+        return choose_explicit(p, A, B, C, uc, L);
+    const int mode = host::picker_mode();
+    tg_config cfg;
+    if ((mode & host::kUseCache) && host::cache_find(key_of(p), &cfg)) {
+        if (choose_explicit(p, A, B, C, &cfg, L) == TG_OK) return TG_OK;
+    }
+    if ((mode & host::kUseMlp) && host::picker_ready()) {
+        std::vector<tg_config> cands;
+        candidates(p, A, B, C, cands);
+        float best = 0.f;
+        int bi = -1;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            Launch Li;
+            if (choose_explicit(p, A, B, C, &cands[i], Li) != TG_OK) continue;
+            float f[TG_PICKER_FEATURES];
+            features(p, Li, f);
+            const float y = host::picker_predict(f);
+            if (bi < 0 || y < best) {
+                best = y;
+                bi = (int)i;
+            }
+        }
+        if (bi >= 0) return choose_explicit(p, A, B, C, &cands[bi], L);
+    }
+    return choose_explicit(p, A, B, C, nullptr, L);
 }
 
 // Program p -> owned sub-tensor ids, as the kernels walk them.
@@ -612,6 +719,31 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
     }
     e = launch_tiled(L.variant, g, hs);
     return e == hipSuccess ? TG_OK : hip_fail(e, "tiled kernel launch");
+}
+
+int32_t tile_gemm_candidates(const tg_in *A, const tg_in *B, const tg_out *C,
+                             const tg_opts *o, tg_config *out, int32_t max) {
+    g_err.clear();
+    Problem p;
+    if (describe(A, B, C, o, p) != TG_OK) return -1;
+    std::vector<tg_config> c;
+    candidates(p, A, B, C, c);
+    for (int32_t i = 0; i < (int32_t)c.size() && i < max; ++i) out[i] = c[i];
+    return (int32_t)c.size();
+}
+
+tg_status tile_picker_features(const tg_in *A, const tg_in *B,
+                               const tg_out *C, const tg_config *cfg,
+                               float *feat) {
+    g_err.clear();
+    if (!feat) return fail(TG_E_ARG, "NULL feature buffer");
+    Problem p;
+    tg_status st = describe(A, B, C, nullptr, p);
+    if (st != TG_OK) return st;
+    Launch L;
+    if ((st = choose_explicit(p, A, B, C, cfg, L)) != TG_OK) return st;
+    features(p, L, feat);
+    return TG_OK;
 }
 
 // ----------------------------------------------------------------- grouped

@@ -99,3 +99,19 @@ def picker_shapes(seed: int, n: int, lo: int = 1, hi: int = 16384):
 
 
 DECODE_SHAPES = [(5120, 5120), (51200, 5120), (5120, 25600)]
+
+
+def mlp_init(n_in: int, hidden: int, depth: int, seed: int) -> torch.Tensor:
+    """Initial cost-model parameters (float32, flat): per layer W (out x in)
+    drawn uniform in +-sqrt(6 / in) (He-uniform), then b = 0; the output
+    layer has one unit."""
+    g = gen(seed)
+    dims = [n_in] + [hidden] * depth + [1]
+    parts = []
+    for l in range(depth + 1):
+        i, o = dims[l], dims[l + 1]
+        lim = math.sqrt(6.0 / i)
+        parts.append((torch.rand((o, i), generator=g, dtype=torch.float64)
+                      * 2 - 1).mul(lim).reshape(-1))
+        parts.append(torch.zeros(o, dtype=torch.float64))
+    return torch.cat(parts).to(torch.float32)

@@ -388,3 +388,75 @@ def test_grouped_matches_oracle_and_single_launches():
         torch.cuda.synchronize()
         for c, e in zip(Cs, eager):
             assert torch.equal(c, e), rep
+
+
+# ------------------------------------------------------------- ragged K
+
+def dev_padded(t, mult=16):
+    """The same values on the GPU, rows starting every ceil(cols / mult) *
+    mult elements (a 16-byte aligned row stride for any element size)."""
+    rows, cols = t.shape
+    ld = (cols + mult - 1) // mult * mult
+    raw = t.view(torch.uint8) if t.dtype == torch.float8_e4m3fn else t
+    buf = torch.zeros((rows, ld), dtype=raw.dtype)
+    buf[:, :cols] = raw
+    out = buf.to(DEV)[:, :cols]
+    return out.view(torch.float8_e4m3fn) if t.dtype == torch.float8_e4m3fn \
+        else out
+
+
+@pytest.mark.parametrize("M,N,K,bm,b_trans", [
+    (300, 264, 37, 64, True), (130, 200, 130, 128, True),
+    (257, 128, 257, 256, True), (96, 80, 9, 32, True),
+    (200, 136, 101, 128, False), (64, 64, 3, 64, False)])
+def test_bf16_tiled_ragged_k(M, N, K, bm, b_trans):
+    note("bf16 ragged K", M, N, K, bm, b_trans)
+    A = synth.to_bf16(synth.normal((M, K), 27))
+    B = synth.to_bf16(synth.normal((N, K) if b_trans else (K, N), 28))
+    C = torch.full((M, N), float("nan"), device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    tg.tile_gemm(dev_padded(A), dev_padded(B), C, bm, bm, b_trans=b_trans,
+                 write_count=wc, config={"kind": "tiled"})
+    torch.cuda.synchronize()
+    assert rel_err(C.cpu(), reference(A, B, b_trans)) <= 1e-5
+    assert torch.all(wc == 1)
+    # small integers: bit-exact
+    Ai = synth.to_bf16(synth.small_int((M, K), 29))
+    Bi = synth.to_bf16(synth.small_int(tuple(B.shape), 30))
+    tg.tile_gemm(dev_padded(Ai), dev_padded(Bi), C, bm, bm, b_trans=b_trans,
+                 config={"kind": "tiled"})
+    torch.cuda.synchronize()
+    assert np.array_equal(exact64(C.cpu()), reference(Ai, Bi, b_trans))
+
+
+@pytest.mark.parametrize("M,N,K,bm", [(100, 90, 37, 64), (256, 200, 130, 128),
+                                      (70, 300, 201, 256)])
+def test_fp8_tiled_ragged_k(M, N, K, bm):
+    note("fp8 ragged K", M, N, K, bm)
+    qa, sa = synth.quant_e4m3_rows(synth.normal((M, K), 37))
+    qb, sb = synth.quant_e4m3_rows(synth.normal((N, K), 38))
+    C = torch.full((M, N), float("nan"), device=DEV)
+    tg.tile_gemm(dev_padded(qa), dev_padded(qb), C, bm, bm, b_trans=True,
+                 scale_a=dev(sa), scale_b=dev(sb), config={"kind": "tiled"})
+    torch.cuda.synchronize()
+    assert rel_err(C.cpu(), reference(qa, qb, True, sa, sb)) <= FP8_BAR
+
+
+@pytest.mark.parametrize("M,K,wdt", [(1, 1001, "bf16"), (8, 1001, "bf16"),
+                                     (8, 1003, "fp8"), (16, 13, "fp8"),
+                                     (3, 5, "bf16")])
+def test_decode_ragged_k(M, K, wdt):
+    N = 200
+    note("decode ragged K", M, N, K, wdt)
+    x = synth.to_bf16(synth.normal((M, K), 45))
+    w = synth.normal((N, K), 46, std=0.02)
+    if wdt == "bf16":
+        W, s = synth.to_bf16(w), None
+    else:
+        W, s = synth.quant_e4m3_rows(w)
+    C = torch.full((M, N), float("nan"), device=DEV)
+    tg.tile_gemm(dev_padded(x), dev_padded(W), C, b_trans=True,
+                 scale_b=None if s is None else dev(s))
+    torch.cuda.synchronize()
+    assert tuple(tg.tile_gemm.last_partition) == (16, 16)
+    assert rel_err(C.cpu(), reference(x, W, True, None, s)) <= 1e-5
