@@ -29,6 +29,42 @@ PEAK_TFLOPS = {"bf16": 2516.6, "fp8": 5033.2, "f32": 157.3}
 PEAK_HBM_GBS = 8000.0
 
 
+KERNEL_SOURCES = ["paper_2606_15991_amd/csrc/gemm_tiled.hip",
+                  "paper_2606_15991_amd/csrc/tg_device.hpp",
+                  "paper_2606_15991_amd/csrc/tg_internal.hpp"]
+TRAFFIC_PROFILE = "profiles/gemm_tiled_bf16_8192_traffic.md"
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the headline kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, when it was taken on the
+    current kernel sources; None otherwise."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip().strip("`").strip("-").strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return int(float(fields["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -110,6 +146,16 @@ def bench_bf16_main(args, tg):
     res = {"M": M, "N": N, "K": K, "ms": ms, "tflops": tflops,
            "ms_unchecked": ms_unchecked, "A": A, "B": B, "C": Cc}
     return res
+
+
+def bench_bf16_nk(args, tg):
+    """Same product with B stored N x K (C = A . B^T of a row-major N x K)."""
+    n = 8192
+    A = synth.to_bf16(synth.normal((n, n), 2)).cuda()
+    B = synth.to_bf16(synth.normal((n, n), 202)).cuda()
+    C = torch.empty((n, n), device="cuda")
+    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256, b_trans=True), 20, 3)
+    return {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
 
 
 def cpu_baseline_and_err(res, target_s):
@@ -234,6 +280,9 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--picker", action="store_true",
+                    help="also run the learned-picker evaluation "
+                         "(2000 training / 200 held-out shapes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
@@ -251,6 +300,15 @@ def main():
         extra.update(bench_f32_and_split(args, tg))
         extra["decode"] = bench_decode(args, tg)
         extra["grouped"] = bench_grouped(args, tg)
+        extra["bf16_8192_b_stored_nk"] = bench_bf16_nk(args, tg)
+    if args.picker:
+        from paper_2606_15991_amd import picker
+        import io
+        import contextlib
+        buf = io.StringIO()
+        with contextlib.redirect_stdout(buf):
+            picker.main([])
+        extra["picker"] = json.loads(buf.getvalue().strip().splitlines()[-1])
     err, cpu, nrows = cpu_baseline_and_err(res, args.cpu_seconds)
     tflops = res["tflops"]
     line = {
@@ -267,13 +325,14 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "bf16 GEMM M=N=K=8192, N(0,1) inputs, "
-                               "f32 accumulate+output, C partition 256x256",
+                               "f32 accumulate+output, C partition 256x256, "
+                               "A and B row-major (B stored K x N)",
                    "M": 8192, "N": 8192, "K": 8192,
                    "partition": [256, 256], "parallelism": "none"},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                      "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(tflops / PEAK_TFLOPS["bf16"], 4),
-                     "traffic": None},
+                     "traffic": traffic_from_profile()},
         "err_rel_fro": err,
         "err_rows": nrows,
         "cpu_baseline": cpu,

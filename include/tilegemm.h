@@ -111,8 +111,9 @@ typedef struct tg_out {
 
 /*
  * Kernel configuration.  bm x bn must equal the output partition; bk is the
- * K-tile depth; wm x wn is the wavefront grid of one workgroup; `kind`
- * selects the kernel family.  Unset fields (0) are filled by the picker.
+ * K-tile depth; wm x wn is the wavefront grid of one workgroup; stages is
+ * the number of K tiles held in LDS at once; `kind` selects the kernel
+ * family.  Unset fields (0) are filled by the picker.
  */
 typedef enum tg_kind {
     TG_KIND_AUTO = 0,
@@ -126,7 +127,7 @@ typedef struct tg_config {
     int32_t bm, bn, bk;
     int32_t wm, wn;
     int32_t ksplit;       /* skinny kernel: wavefronts sharing one tile's K  */
-    int32_t reserved;
+    int32_t stages;       /* tiled kernel: LDS stages of the K-tile ring     */
 } tg_config;
 
 typedef struct tg_opts {
@@ -288,17 +289,19 @@ tg_status tile_tune_cache_load(const char *path);
 
 /*
  * Picker.  TG_PICKER_FEATURES numbers describe a (request, configuration)
- * pair: log2 M, N, K; e4m3 / f32 operand flags; B stored N x K; kernel kind
- * (three one-hot flags); log2 bm, bn, ksplit; log2 of the sub-tensor count
- * and of the sub-tensors per program; useful fraction of the padded output
- * area; log2 of 2MNK.  tile_picker_set installs a cost model (host copy of
- * the parameters in the layout of tile_mlp_*, with per-feature mean and
- * standard deviation used to normalise the features); params == NULL
- * removes it.  tile_picker_mode(mode) sets bit 1 = use the tuning cache,
- * bit 2 = use the cost model (mode < 0 only queries) and returns the
- * previous mode.
+ * pair, in this order: log2 M, N, K; flags for e4m3 operands, f32 operands,
+ * B stored N x K and a bf16 output; the kernel kind (three one-hot flags:
+ * tiled, skinny, simple); log2 bm, bn, wavefronts per program, LDS stages
+ * and ksplit; log2 of the sub-tensor count, of the program count and of the
+ * sub-tensors per program; the fraction of the last round of sub-tensors
+ * that has work; the useful fraction of the padded output area.
+ * tile_picker_set installs a cost model (host copy of the parameters in the
+ * layout of tile_mlp_*, with per-feature mean and standard deviation used
+ * to normalise the features); params == NULL removes it.
+ * tile_picker_mode(mode) sets bit 1 = use the tuning cache, bit 2 = use the
+ * cost model (mode < 0 only queries) and returns the previous mode.
  */
-#define TG_PICKER_FEATURES 16
+#define TG_PICKER_FEATURES 20
 tg_status tile_picker_features(const tg_in *A, const tg_in *B,
                                const tg_out *C, const tg_config *cfg,
                                float *feat);
@@ -317,7 +320,10 @@ int32_t tile_picker_mode(int32_t mode);
  *   tile_mlp_loss_grad: loss (device, 1 value) = mean (MLP(X) - y)^2 and
  *                       grads (device, same layout as params) = dloss/dparams
  *   tile_mlp_adam:      one Adam step (Kingma & Ba) at step t >= 1 on n
- *                       parameters with moment buffers m, v (device)
+ *                       parameters with moment buffers m, v (device); the
+ *                       hyper-parameters are binary64 so that 1 - beta and
+ *                       the bias corrections are formed before any rounding
+ *                       to binary32
  * ws (device) holds activations: tile_mlp_workspace_bytes bytes.  All
  * reductions run in a fixed order: repeated calls give identical results.
  */
@@ -334,8 +340,8 @@ tg_status tile_mlp_loss_grad(const float *params, int32_t n_in,
                              float *loss, void *ws, size_t ws_bytes,
                              tg_stream stream);
 tg_status tile_mlp_adam(float *params, const float *grads, float *m, float *v,
-                        int64_t n, float lr, float beta1, float beta2,
-                        float eps, int32_t t, tg_stream stream);
+                        int64_t n, double lr, double beta1, double beta2,
+                        double eps, int32_t t, tg_stream stream);
 
 const char *tg_status_str(int32_t status);
 const char *tg_last_error(void);

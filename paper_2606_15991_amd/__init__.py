@@ -56,11 +56,10 @@ class tg_config(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("bm", ctypes.c_int32),
                 ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
                 ("wm", ctypes.c_int32), ("wn", ctypes.c_int32),
-                ("ksplit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ksplit", ctypes.c_int32), ("stages", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: int(getattr(self, f)) for f, _ in self._fields_
-                if f != "reserved"}
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class tg_opts(ctypes.Structure):
@@ -77,7 +76,7 @@ class tg_tune_result(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
-TG_PICKER_FEATURES = 16
+TG_PICKER_FEATURES = 20
 
 
 class TileGemmError(RuntimeError):
@@ -148,8 +147,8 @@ def _load():
     lib.tile_mlp_loss_grad.argtypes = [vp, i32, i32, i32, vp, vp, i32, vp,
                                        vp, vp, ctypes.c_size_t, vp]
     lib.tile_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int64,
-                                  ctypes.c_float, ctypes.c_float,
-                                  ctypes.c_float, ctypes.c_float, i32, vp]
+                                  ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, i32, vp]
     for f in ("tile_autotune", "tile_tune_cache_clear", "tile_tune_cache_save",
               "tile_tune_cache_load", "tile_picker_features",
               "tile_picker_set", "tile_picker_predict", "tile_mlp_forward",
@@ -194,7 +193,9 @@ def _ld(t: torch.Tensor) -> int:
         raise TileGemmError(TG_E_SHAPE, "operands are 2-D matrices")
     if t.shape[1] > 1 and t.stride(1) != 1:
         raise TileGemmError(TG_E_SHAPE, "rows must be contiguous")
-    return int(t.stride(0)) if t.shape[0] > 1 else int(max(t.shape[1], 1))
+    if t.shape[0] > 1 or t.stride(0) >= t.shape[1]:
+        return int(t.stride(0))
+    return int(max(t.shape[1], 1))
 
 
 def make_in(t: torch.Tensor, trans: bool = False) -> tg_in:

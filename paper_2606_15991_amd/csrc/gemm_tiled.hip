@@ -7,7 +7,8 @@
 // into its own BM x BN sub-tensor only.  A and B are read-only.
 //
 // gfx950 design:
-//   * every K tile is 128 bytes deep (64 bf16, 32 f32 or 128 e4m3);
+//   * every K tile is RBY = 128 or 64 bytes deep per row (bf16: 64 or 32
+//     elements, e4m3: 128 or 64, f32: 32);
 //   * k-contiguous operands (A, and B stored N x K) live in LDS as
 //     [rows][128 B] with the 16-byte chunk index XOR-swizzled per row so
 //     that the 16-byte fragment reads are free of bank conflicts;
@@ -20,9 +21,12 @@
 //   * a bf16 B stored K x N stays k-major in LDS ([BK][BN], chunk index
 //     XOR-swizzled by k & 3) and is read with the transposing LDS read,
 //     which hands each lane four consecutive k of one column;
-//   * two LDS stages: the next K tile streams into stage s ^ 1 while the
-//     MFMAs consume stage s; one barrier per K tile; the first stage of the
-//     program's next sub-tensor is fetched while the current one is stored;
+//   * a ring of NS = 2 or 4 LDS stages: the loads of the next NS - 1 K tiles
+//     are in flight while the MFMAs consume the current one (the HBM/L2
+//     latency under full load is about the time of one 64-deep step, so the
+//     deeper ring with 32-deep tiles keeps the matrix cores fed); one barrier
+//     per K tile; the first K tiles of the program's next sub-tensor are
+//     fetched while the current one is stored;
 //   * f32 tiles go through registers (B stored K x N transposed 4 x 4 in
 //     registers), pipelined the same way;
 //   * in the f32 register path rows of A beyond M and columns of B beyond N
@@ -55,44 +59,65 @@ struct DtypeTraits<TG_FP8_E4M3> {
     static constexpr int ES = 1;
 };
 
-template <int DT, int BM_, int BN_, int WM_, int WN_, bool BNK_, bool CBF16_>
+template <int DT, int BM_, int BN_, int WM_, int WN_, bool BNK_, bool CBF16_,
+          int RBY_ = 128, int NS_ = 2>
 struct Cfg {
     static constexpr int DTYPE = DT;
     static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
     static constexpr bool BNK = BNK_, CBF16 = CBF16_;
     static constexpr int ES = DtypeTraits<DT>::ES;
     static constexpr int EPC = 16 / ES;         // elements per 16-byte chunk
-    static constexpr int BK = 128 / ES;         // K elements per K tile
+    static constexpr int RBY = RBY_;            // bytes of K per operand row
+    static constexpr int NS = NS_;              // LDS stages in the ring
+    static constexpr int BK = RBY / ES;         // K elements per K tile
+    static constexpr int CPRW = RBY / 16;       // 16-byte chunks per row
+    static constexpr int RPK = 1024 / RBY;      // rows per 1 KiB block
     static constexpr int NW = WM * WN;          // wavefronts
     static constexpr int THREADS = NW * 64;
     static constexpr int TM = BM / WM, TN = BN / WN;
     static constexpr int FM = TM / 32, FN = TN / 32;
-    static constexpr bool DIRECT = ES <= 2;     // direct global->LDS loads
+    static constexpr bool DIRECT = ES <= 2;     // direct buffer->LDS loads
     static constexpr bool B_KMAJOR = !BNK && ES == 2;  // [BK][BN] in LDS
     static constexpr int RB = BN * ES;          // bytes per k-major B row
     static constexpr int CPR = RB / 16;         // chunks per k-major B row
-    static constexpr int A_CH = BM * 8 / THREADS;   // A chunks per thread
-    static constexpr int B_CH = BN * 8 / THREADS;   // B chunks per thread
+    static constexpr int A_CH = BM * 8 / THREADS;   // f32 path: A chunks
+    static constexpr int B_CH = BN * 8 / THREADS;   // f32 path: B chunks
     // f32 B stored K x N: EPC x EPC blocks, (BK / EPC) * (BN / EPC) of them
     static constexpr int B_BLK = (BK / EPC) * (BN / EPC);
     static constexpr int B_BLK_PT = (B_BLK + THREADS - 1) / THREADS;
-    static constexpr int STAGE = (BM + BN) * 128;   // bytes per LDS stage
+    static constexpr int STAGE = (BM + BN) * RBY;   // bytes per LDS stage
+    static constexpr int LPW = STAGE / 1024 / NW;   // 1 KiB loads per wave
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
-    static_assert((BM * 8) % THREADS == 0, "A chunk split");
-    static_assert((BN * 8) % THREADS == 0, "B chunk split");
-    static_assert((BM / 8) % NW == 0 && (BN / 8) % NW == 0, "1 KiB blocks");
+    static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
+    static_assert(NS == 2 || NS == 4, "ring of 2 or 4 stages");
+    static_assert(DIRECT || (RBY == 128 && NS == 2), "f32 register path");
+    static_assert((BM / RPK) % NW == 0, "A 1 KiB blocks per wave");
+    static_assert(B_KMAJOR ? (BK * RB / 1024) % NW == 0
+                           : (BN / RPK) % NW == 0, "B 1 KiB blocks per wave");
+    static_assert(DIRECT || ((BM * 8) % THREADS == 0 &&
+                             (BN * 8) % THREADS == 0), "f32 chunk split");
     static_assert(BNK || DT != TG_FP8_E4M3, "e4m3 B must be stored N x K");
     static_assert(!B_KMAJOR || CPR >= 4, "k-major B rows of >= 64 bytes");
+    static_assert(DT != TG_FP8_E4M3 || BK >= 64, "e4m3 K tile >= 64");
+    static_assert(LPW * (NS - 2) < 64, "vmcnt range");
 };
 
-// Row-major [rows][128 B] operand stage: chunk c of row r sits at chunk
-// position c ^ f(r), f(r) = (r ^ (r >> 3)) & 7.  Any 16 consecutive rows
-// read at one logical chunk then cover 16 distinct 16-byte bank groups of a
+// Row-major [rows][RBY bytes] operand stage: chunk c of row r sits at chunk
+// position c ^ f(r), with f(r) = (r ^ (r >> 3)) & 7 for 128-byte rows and
+// ((r >> 1) ^ (r >> 3)) & 3 for 64-byte rows.  Any 16 consecutive rows read
+// at one logical chunk then cover 16 distinct 16-byte bank groups of a
 // 256-byte bank window (and any 8 of them 8 groups of a 128-byte window), so
 // the 16-byte fragment reads are conflict-free.
-__device__ __forceinline__ int swz_f(int row) { return (row ^ (row >> 3)) & 7; }
+template <class C>
+__device__ __forceinline__ int swz_f(int row) {
+    if constexpr (C::RBY == 128)
+        return (row ^ (row >> 3)) & 7;
+    else
+        return ((row >> 1) ^ (row >> 3)) & 3;
+}
+template <class C>
 __device__ __forceinline__ int swz(int row, int chunk) {
-    return row * 128 + ((chunk ^ swz_f(row)) << 4);
+    return row * C::RBY + ((chunk ^ swz_f<C>(row)) << 4);
 }
 
 // Chunk permutation of k-major B rows, by k & 3: the four rows of a 16-lane
@@ -112,6 +137,23 @@ __device__ __forceinline__ int swz_kmajor(int k) {
 
 __device__ __forceinline__ void wait_vmem() {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmem_le() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+
+// Workgroup barrier for the K-tile ring.  __syncthreads() carries a
+// workgroup-scope fence, which waits for every outstanding global access of
+// the wavefront, including the loads of later K tiles that must stay in
+// flight.  The ring needs less: this wavefront's LDS reads are complete (so
+// a stage may be overwritten after the barrier) and the loads of the tile
+// about to be read have landed (waited for by the caller).
+__device__ __forceinline__ void ring_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 // One owned sub-tensor as the kernels see it.
@@ -152,50 +194,40 @@ __device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
 }
 
 // Direct HBM -> LDS issue of K tile k0 of one owned sub-tensor.  Each lane
-// fetches the 16-byte chunk that the LDS swizzle places at its position.
-// Rows beyond M / N and K beyond the operand read as zeros (out-of-range
-// buffer offsets), so the K tail needs no separate path.
+// fetches the 16-byte chunk that the LDS swizzle places at its position:
+// lane l of the 1 KiB block rb writes row rb * RPK + l / CPRW at chunk
+// position l % CPRW, which holds logical chunk (l % CPRW) ^ f(row).  Rows
+// beyond M / N and chunks not wholly inside K read as zeros (out-of-range
+// buffer offsets); a chunk straddling K is filled by fill_k_tail.
+template <class C, int ROWS>
+__device__ __forceinline__ void issue_operand(const char *mat, int64_t ld,
+                                              int r0, int rows, int k0,
+                                              int K, char *dst, int wave,
+                                              int lane) {
+    const char *base = mat + ((int64_t)r0 * ld + k0) * C::ES;
+    const uint32_t nrec = sat_bytes(((int64_t)(rows - r0) * ld - k0) * C::ES);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
+    const int rsub = lane / C::CPRW, p = lane % C::CPRW;
+#pragma unroll
+    for (int i = 0; i < ROWS / C::RPK / C::NW; ++i) {
+        const int rb = i * C::NW + wave;
+        const int row = rb * C::RPK + rsub;           // row within the tile
+        const int kc = p ^ swz_f<C>(row);
+        const bool kin = k0 + (kc + 1) * C::EPC <= K;
+        buf_to_lds(r, dst + rb * 1024,
+                   kin ? (uint32_t)((row * ld + kc * C::EPC) * C::ES)
+                       : kOutOfRange);
+    }
+}
+
 template <class C>
 __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
                                              int k0, int wave, int lane) {
-    // lane l of the 1 KiB block of rows 8 rb .. 8 rb + 7 writes row
-    // 8 rb + l / 8 at chunk position l % 8, which holds logical chunk
-    // (l % 8) ^ f(row) = (l % 8) ^ (l / 8) ^ (rb % 8)
-    const int rsub = lane >> 3;
-    const int kc0 = (lane & 7) ^ rsub;
-    {
-        // A rows m0.. : descriptor from (m0, k0); rows >= M are past its end
-        const char *base = j.a + ((int64_t)j.m0 * j.lda + k0) * C::ES;
-        const uint32_t nrec =
-            sat_bytes(((int64_t)(j.M - j.m0) * j.lda - k0) * C::ES);
-        const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
-        const uint32_t off0 = (uint32_t)((wave * 8 + rsub) * j.lda * C::ES);
-        const uint32_t step = (uint32_t)(C::NW * 8 * j.lda * C::ES);
-#pragma unroll
-        for (int i = 0; i < C::BM / 8 / C::NW; ++i) {
-            const int rb = i * C::NW + wave;
-            const int kc = kc0 ^ (rb & 7);
-            const bool kin = k0 + (kc + 1) * C::EPC <= j.K;
-            buf_to_lds(r, stage + rb * 1024,
-                       kin ? off0 + i * step + kc * 16 : kOutOfRange);
-        }
-    }
-    char *Bs = stage + C::BM * 128;
+    issue_operand<C, C::BM>(j.a, j.lda, j.m0, j.M, k0, j.K, stage, wave, lane);
+    char *Bs = stage + C::BM * C::RBY;
     if constexpr (!C::B_KMAJOR) {
-        const char *base = j.b + ((int64_t)j.n0 * j.ldb + k0) * C::ES;
-        const uint32_t nrec =
-            sat_bytes(((int64_t)(j.N - j.n0) * j.ldb - k0) * C::ES);
-        const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
-        const uint32_t off0 = (uint32_t)((wave * 8 + rsub) * j.ldb * C::ES);
-        const uint32_t step = (uint32_t)(C::NW * 8 * j.ldb * C::ES);
-#pragma unroll
-        for (int i = 0; i < C::BN / 8 / C::NW; ++i) {
-            const int rb = i * C::NW + wave;
-            const int kc = kc0 ^ (rb & 7);
-            const bool kin = k0 + (kc + 1) * C::EPC <= j.K;
-            buf_to_lds(r, Bs + rb * 1024,
-                       kin ? off0 + i * step + kc * 16 : kOutOfRange);
-        }
+        issue_operand<C, C::BN>(j.b, j.ldb, j.n0, j.N, k0, j.K, Bs, wave,
+                                lane);
     } else {
         // k-major B: descriptor from (k0, n0); rows k >= K are past its end,
         // columns >= N are masked per lane
@@ -204,7 +236,7 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
             sat_bytes(((int64_t)(j.K - k0) * j.ldb - j.n0) * C::ES);
         const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
 #pragma unroll
-        for (int i = 0; i < C::BN / 8 / C::NW; ++i) {
+        for (int i = 0; i < C::BK * C::RB / 1024 / C::NW; ++i) {
             const int gi = i * C::NW + wave;
             const int off = gi * 1024 + lane * 16;
             const int k = off / C::RB;
@@ -274,17 +306,17 @@ struct RegTile {
 
     __device__ __forceinline__ void store(char *stage, int tid) {
         char *As = stage;
-        char *Bs = stage + C::BM * 128;
+        char *Bs = stage + C::BM * C::RBY;
 #pragma unroll
         for (int i = 0; i < C::A_CH; ++i) {
             const int q = i * C::THREADS + tid;
-            st16(As + swz(q >> 3, q & 7), ra[i]);
+            st16(As + swz<C>(q >> 3, q & 7), ra[i]);
         }
         if constexpr (C::BNK) {
 #pragma unroll
             for (int i = 0; i < C::B_CH; ++i) {
                 const int q = i * C::THREADS + tid;
-                st16(Bs + swz(q >> 3, q & 7), rb[i]);
+                st16(Bs + swz<C>(q >> 3, q & 7), rb[i]);
             }
         } else {
             // f32 B stored K x N: 4 x 4 blocks (rows k, columns n) become
@@ -299,7 +331,7 @@ struct RegTile {
                     reinterpret_cast<const uint32_t *>(&rb[i * C::EPC]);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
-                    st16(Bs + swz(nb * 4 + c, kb),
+                    st16(Bs + swz<C>(nb * 4 + c, kb),
                          uint4{w[0 * 4 + c], w[1 * 4 + c], w[2 * 4 + c],
                                w[3 * 4 + c]});
             }
@@ -340,7 +372,7 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
                                               int wn, int lane,
                                               f32x16 (&acc)[C::FM][C::FN]) {
     const char *As = stage;
-    const char *Bs = stage + C::BM * 128;
+    const char *Bs = stage + C::BM * C::RBY;
     const int r = lane & 31, half = lane >> 5;
     if constexpr (C::DTYPE == TG_BF16 || C::DTYPE == TG_F32) {
         // fragments of step kk + 1 are read while the MFMAs of step kk run
@@ -350,7 +382,7 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
 #pragma unroll
             for (int f = 0; f < C::FM; ++f)
                 af[s][f] = *reinterpret_cast<const i32x4 *>(
-                    As + swz(wm * C::TM + f * 32 + r, c));
+                    As + swz<C>(wm * C::TM + f * 32 + r, c));
 #pragma unroll
             for (int f = 0; f < C::FN; ++f) {
                 if constexpr (C::B_KMAJOR)
@@ -358,19 +390,20 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
                                                  lane);
                 else
                     bfr[s][f] = *reinterpret_cast<const i32x4 *>(
-                        Bs + swz(wn * C::TN + f * 32 + r, c));
+                        Bs + swz<C>(wn * C::TN + f * 32 + r, c));
             }
         };
+        constexpr int KK = C::DTYPE == TG_BF16 ? C::BK / 16 : C::BK / 8;
         load(0, 0);
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
+        for (int kk = 0; kk < KK; ++kk) {
             const int s = kk & 1;
-            if (kk + 1 < 4) load(kk + 1, s ^ 1);
+            if (kk + 1 < KK) load(kk + 1, s ^ 1);
             if constexpr (C::DTYPE == TG_BF16 && C::FM * C::FN >= 8) {
                 // interleave the next step's LDS reads with this step's
                 // MFMAs: one read after each of the first MFMAs
                 constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
-                if (kk + 1 < 4) {
+                if (kk + 1 < KK) {
 #pragma unroll
                     for (int q = 0; q < NR; ++q) {
                         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -396,24 +429,24 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
         }
     } else {
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
+        for (int kk = 0; kk < C::BK / 64; ++kk) {
             const int c = 4 * kk + 2 * half;
             i32x8 af[C::FM], bfr[C::FN];
 #pragma unroll
             for (int f = 0; f < C::FM; ++f) {
                 const int row = wm * C::TM + f * 32 + r;
-                i32x4 lo = *reinterpret_cast<const i32x4 *>(As + swz(row, c));
+                i32x4 lo = *reinterpret_cast<const i32x4 *>(As + swz<C>(row, c));
                 i32x4 hi =
-                    *reinterpret_cast<const i32x4 *>(As + swz(row, c + 1));
+                    *reinterpret_cast<const i32x4 *>(As + swz<C>(row, c + 1));
                 af[f] = i32x8{lo[0], lo[1], lo[2], lo[3],
                               hi[0], hi[1], hi[2], hi[3]};
             }
 #pragma unroll
             for (int f = 0; f < C::FN; ++f) {
                 const int row = wn * C::TN + f * 32 + r;
-                i32x4 lo = *reinterpret_cast<const i32x4 *>(Bs + swz(row, c));
+                i32x4 lo = *reinterpret_cast<const i32x4 *>(Bs + swz<C>(row, c));
                 i32x4 hi =
-                    *reinterpret_cast<const i32x4 *>(Bs + swz(row, c + 1));
+                    *reinterpret_cast<const i32x4 *>(Bs + swz<C>(row, c + 1));
                 bfr[f] = i32x8{lo[0], lo[1], lo[2], lo[3],
                                hi[0], hi[1], hi[2], hi[3]};
             }
@@ -454,20 +487,29 @@ __device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
                                                                 jj * 32]
                                                      : 1.0f;
     const uint32_t lane_off = (uint32_t)((r0 * j.ldc + c0) * OES);
+    // every scale is loaded before the first store: a wait for a load
+    // issued after stores would also wait for those stores (one counter)
+    float sa[C::FM][16];
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
+            sa[i][v] = (j.scale_a && dr < rows_left)
+                           ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
+        }
 #pragma unroll
     for (int i = 0; i < C::FM; ++i) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
             const bool row_ok = dr < rows_left;
-            const float sa =
-                (j.scale_a && row_ok) ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
             const uint32_t roff = lane_off + (uint32_t)(dr * j.ldc * OES);
 #pragma unroll
             for (int jj = 0; jj < C::FN; ++jj) {
                 const bool ok = row_ok && jj * 32 < cols_left;
                 const uint32_t off = ok ? roff + jj * 32 * OES : kOutOfRange;
-                const float x = acc[i][jj][v] * sb[jj] * sa;
+                const float x = acc[i][jj][v] * sb[jj] * sa[i][v];
                 if constexpr (C::CBF16)
                     __builtin_amdgcn_raw_buffer_store_b16(
                         (unsigned short)f32_to_bf16_bits(x), r, off, 0, 0);
@@ -517,7 +559,7 @@ __device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
     const int chunk = (kbase - k0) / C::EPC;      // its logical chunk index
     for (int r = tid; r < C::BM; r += C::THREADS) {
         const int row = j.m0 + r;
-        char *dst = stage + swz(r, chunk);
+        char *dst = stage + swz<C>(r, chunk);
         const char *src = j.a + ((int64_t)row * j.lda + kbase) * C::ES;
         for (int e = 0; e < rem; ++e) {
             if constexpr (C::ES == 2)
@@ -529,10 +571,10 @@ __device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
         }
     }
     if constexpr (!C::B_KMAJOR) {
-        char *Bs = stage + C::BM * 128;
+        char *Bs = stage + C::BM * C::RBY;
         for (int r = tid; r < C::BN; r += C::THREADS) {
             const int row = j.n0 + r;
-            char *dst = Bs + swz(r, chunk);
+            char *dst = Bs + swz<C>(r, chunk);
             const char *src = j.b + ((int64_t)row * j.ldb + kbase) * C::ES;
             for (int e = 0; e < rem; ++e) {
                 if constexpr (C::ES == 2)
@@ -550,8 +592,31 @@ __device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
 
 // ------------------------------------------------------- persistent loops
 
+// Wait until the loads of one K tile have landed while the loads of the
+// `later` tiles issued after it (0 <= later <= NS - 2) may still be in
+// flight: every wavefront issues the same LPW loads per tile, in tile order.
+template <class C>
+__device__ __forceinline__ void wait_tile(int later) {
+    if constexpr (C::NS >= 4) {
+        if (later >= 2) {
+            wait_vmem_le<2 * C::LPW>();
+            return;
+        }
+    }
+    if constexpr (C::NS >= 3) {
+        if (later >= 1) {
+            wait_vmem_le<C::LPW>();
+            return;
+        }
+    }
+    wait_vmem();
+}
+
 // Direct-load programs (bf16, e4m3).  P provides the owned sub-tensors:
-// P::n_prog(), P::count(), P::job(t).
+// P::n_prog(), P::count(), P::job(t).  The K tiles of all owned sub-tensors
+// flow through a ring of NS LDS stages (running index g): tile g lives in
+// stage g % NS, and the loads of tiles g+1 .. g+NS-2 are in flight while
+// tile g is contracted.
 template <class C, class P>
 __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
     const int tid = threadIdx.x;
@@ -560,40 +625,50 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
     const int G = prov.n_prog(), total = prov.count();
     int t = program_slot(blockIdx.x, G);
     if (t >= total) return;
+    auto stage = [&](int g) { return smem + (g % C::NS) * C::STAGE; };
     Job j = prov.job(t);
-    if (j.K > 0) issue_direct<C>(j, smem, 0, wave, lane);  // stage 0
+    int g = 0;
+    {
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        for (int s = 0; s < C::NS - 1 && s < nk; ++s)
+            issue_direct<C>(j, stage(g + s), s * C::BK, wave, lane);
+    }
     f32x16 acc[C::FM][C::FN];
     while (true) {
         const int nk = (j.K + C::BK - 1) / C::BK;
         // the last K tile holds a chunk that straddles K
         const bool ragged = (j.K % C::EPC) != 0;
-        wait_vmem();
-        __syncthreads();
-        if (ragged && nk == 1) {
-            fill_k_tail<C>(j, smem, 0, tid);
-            __syncthreads();
-        }
         zero_acc<C>(acc);
+        if (nk == 0) ring_barrier();
         for (int kt = 0; kt < nk; ++kt) {
-            if (kt + 1 < nk)
-                issue_direct<C>(j, smem + ((kt + 1) & 1) * C::STAGE,
-                                (kt + 1) * C::BK, wave, lane);
-            compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc);
-            wait_vmem();
-            __syncthreads();
-            if (ragged && kt + 2 == nk) {
-                fill_k_tail<C>(j, smem + ((kt + 1) & 1) * C::STAGE,
-                               (kt + 1) * C::BK, tid);
+            const int later = nk - 1 - kt < C::NS - 2 ? nk - 1 - kt : C::NS - 2;
+            if (kt == 0)
+                wait_vmem();   // also covers the previous sub-tensor's stores
+            else
+                wait_tile<C>(later);
+            ring_barrier();
+            if (ragged && kt == nk - 1) {
+                fill_k_tail<C>(j, stage(g + kt), kt * C::BK, tid);
                 __syncthreads();
             }
+            // the stage of tile kt - 1 is free: every wavefront passed the
+            // barrier above after contracting it
+            if (kt + C::NS - 1 < nk)
+                issue_direct<C>(j, stage(g + kt + C::NS - 1),
+                                (kt + C::NS - 1) * C::BK, wave, lane);
+            compute_stage<C>(stage(g + kt), wm, wn, lane, acc);
         }
-        // fetch stage 0 of the next owned sub-tensor, then store this one
+        g += nk;
+        // first tiles of the next owned sub-tensor, then store this one; the
+        // stages written now are all but the one of the last tile contracted
         t += G;
         const bool more = t < total;
         Job nj;
         if (more) {
             nj = prov.job(t);
-            if (nj.K > 0) issue_direct<C>(nj, smem, 0, wave, lane);
+            const int nk2 = (nj.K + C::BK - 1) / C::BK;
+            for (int s = 0; s < C::NS - 1 && s < nk2; ++s)
+                issue_direct<C>(nj, stage(g + s), s * C::BK, wave, lane);
         }
         epilogue<C>(j, wm, wn, lane, acc);
         if (!more) break;
@@ -723,39 +798,46 @@ template <class C>
 VariantEntry make_entry() {
     VariantEntry e;
     e.v.dtype = C::DTYPE;
-    e.v.bm = C::BM; e.v.bn = C::BN; e.v.bk = C::BK;
+    e.v.bm = C::BM; e.v.bn = C::BN; e.v.bk = C::BK; e.v.stages = C::NS;
     e.v.wm = C::WM; e.v.wn = C::WN;
     e.v.b_nk = C::BNK; e.v.c_bf16 = C::CBF16;
     e.kernel = reinterpret_cast<const void *>(&gemm_tiled_kernel<C>);
     e.grouped = reinterpret_cast<const void *>(&gemm_grouped_kernel<C>);
     e.threads = C::THREADS;
-    e.smem = 2 * C::STAGE;
+    e.smem = C::NS * C::STAGE;
     return e;
 }
 
-#define TG_VARIANTS_FOR(DT, BM, BN, WM, WN)                      \
-    make_entry<Cfg<DT, BM, BN, WM, WN, false, false>>(),        \
-        make_entry<Cfg<DT, BM, BN, WM, WN, false, true>>(),     \
-        make_entry<Cfg<DT, BM, BN, WM, WN, true, false>>(),     \
-        make_entry<Cfg<DT, BM, BN, WM, WN, true, true>>()
+#define TG_VARIANTS_FOR(DT, BM, BN, WM, WN, RBY, NS)                          \
+    make_entry<Cfg<DT, BM, BN, WM, WN, false, false, RBY, NS>>(),             \
+        make_entry<Cfg<DT, BM, BN, WM, WN, false, true, RBY, NS>>(),          \
+        make_entry<Cfg<DT, BM, BN, WM, WN, true, false, RBY, NS>>(),          \
+        make_entry<Cfg<DT, BM, BN, WM, WN, true, true, RBY, NS>>()
 
-#define TG_VARIANTS_NK(DT, BM, BN, WM, WN)                       \
-    make_entry<Cfg<DT, BM, BN, WM, WN, true, false>>(),         \
-        make_entry<Cfg<DT, BM, BN, WM, WN, true, true>>()
+#define TG_VARIANTS_NK(DT, BM, BN, WM, WN, RBY, NS)                           \
+    make_entry<Cfg<DT, BM, BN, WM, WN, true, false, RBY, NS>>(),              \
+        make_entry<Cfg<DT, BM, BN, WM, WN, true, true, RBY, NS>>()
 
+// Table order is preference order: the first variant matching a request's
+// dtype, partition, layout and output type is the default.
 const VariantEntry *table(int *count) {
     static const VariantEntry entries[] = {
-        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 2),
-        TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2),
-        TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2),
-        TG_VARIANTS_FOR(TG_BF16, 32, 32, 1, 1),
-        TG_VARIANTS_FOR(TG_F32, 128, 128, 2, 2),
-        TG_VARIANTS_FOR(TG_F32, 64, 64, 2, 2),
-        TG_VARIANTS_FOR(TG_F32, 32, 32, 1, 1),
-        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 2),
-        TG_VARIANTS_NK(TG_FP8_E4M3, 128, 128, 2, 2),
-        TG_VARIANTS_NK(TG_FP8_E4M3, 64, 64, 2, 2),
-        TG_VARIANTS_NK(TG_FP8_E4M3, 32, 32, 1, 1),
+        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 64, 4),
+        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 2, 64, 4),
+        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 128, 2),
+        TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
+        TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 128, 2),
+        TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2, 128, 2),
+        TG_VARIANTS_FOR(TG_BF16, 32, 32, 1, 1, 128, 2),
+        TG_VARIANTS_FOR(TG_F32, 128, 128, 2, 2, 128, 2),
+        TG_VARIANTS_FOR(TG_F32, 64, 64, 2, 2, 128, 2),
+        TG_VARIANTS_FOR(TG_F32, 32, 32, 1, 1, 128, 2),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 2, 128, 2),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 4, 64, 4),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 4, 128, 2),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 128, 128, 2, 2, 128, 2),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 64, 64, 2, 2, 128, 2),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 32, 32, 1, 1, 128, 2),
     };
     *count = (int)(sizeof(entries) / sizeof(entries[0]));
     return entries;

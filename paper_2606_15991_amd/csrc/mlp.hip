@@ -98,15 +98,17 @@ __global__ void dense_bwd_input(const float *__restrict__ dZ,
 
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
 // p -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
+// The constants 1 - b1, 1 - b2 and the bias corrections are formed in
+// binary64 on the host: 1 - 0.999 in binary32 loses 4 significant digits.
 __global__ void adam_step(float *__restrict__ p, const float *__restrict__ g,
                           float *__restrict__ m, float *__restrict__ v,
-                          int64_t n, float lr, float b1, float b2, float eps,
-                          float c1, float c2) {
+                          int64_t n, float lr, float b1, float b2, float omb1,
+                          float omb2, float eps, float c1, float c2) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     const float gi = g[e];
-    const float mi = b1 * m[e] + (1.0f - b1) * gi;
-    const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+    const float mi = b1 * m[e] + omb1 * gi;
+    const float vi = b2 * v[e] + omb2 * (gi * gi);
     m[e] = mi;
     v[e] = vi;
     p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -241,15 +243,17 @@ tg_status tile_mlp_loss_grad(const float *params, int32_t n_in,
 }
 
 tg_status tile_mlp_adam(float *params, const float *grads, float *m, float *v,
-                        int64_t n, float lr, float beta1, float beta2,
-                        float eps, int32_t t, tg_stream stream) {
+                        int64_t n, double lr, double beta1, double beta2,
+                        double eps, int32_t t, tg_stream stream) {
     if (!params || !grads || !m || !v || n < 0 || t < 1) return TG_E_ARG;
     if (n == 0) return TG_OK;
-    const float c1 = 1.0f - powf(beta1, (float)t);
-    const float c2 = 1.0f - powf(beta2, (float)t);
+    const float c1 = (float)(1.0 - pow(beta1, (double)t));
+    const float c2 = (float)(1.0 - pow(beta2, (double)t));
     hipLaunchKernelGGL(adam_step, dim3(blocks_for(n, 256)), dim3(256), 0,
                        static_cast<hipStream_t>(stream), params, grads, m, v,
-                       n, lr, beta1, beta2, eps, c1, c2);
+                       n, (float)lr, (float)beta1, (float)beta2,
+                       (float)(1.0 - beta1), (float)(1.0 - beta2), (float)eps,
+                       c1, c2);
     return hipGetLastError() == hipSuccess ? TG_OK : TG_E_HIP;
 }
 

@@ -93,6 +93,7 @@ struct GroupHeader {
 struct TiledVariant {
     int32_t dtype;   // tg_dtype of A and B
     int32_t bm, bn, bk, wm, wn;
+    int32_t stages;  // LDS stages in the K-tile ring
     int32_t b_nk;
     int32_t c_bf16;
 };

@@ -215,7 +215,9 @@ bool tiled_ok(const Problem &p, const tg_in *A, const tg_in *B,
     if (p.a_dt != p.b_dt) return false;
     if (dt == TG_FP8_E4M3 && !p.b_nk) return false;
     if (!aligned16(A->data) || !aligned16(B->data)) return false;
-    if ((A->ld * es) % 16 || (B->ld * es) % 16) return false;
+    // row starts must stay 16-byte aligned (a single row has no stride)
+    if ((A->rows > 1 && (A->ld * es) % 16) || (B->rows > 1 && (B->ld * es) % 16))
+        return false;
     // bf16 / e4m3 take any K (the straddling chunk is filled element-wise);
     // the f32 register path needs whole 16-byte chunks
     if (dt == TG_F32 && p.K % epc) return false;
@@ -232,18 +234,21 @@ bool skinny_ok(const Problem &p, const tg_in *A, const tg_in *B) {
     if (p.M > 16 || !p.b_nk || p.a_dt != TG_BF16) return false;
     if (p.b_dt != TG_BF16 && p.b_dt != TG_FP8_E4M3) return false;
     if (!aligned16(A->data) || !aligned16(B->data)) return false;
-    if ((A->ld * 2) % 16 || (B->ld * esize(p.b_dt)) % 16) return false;
+    if ((A->rows > 1 && (A->ld * 2) % 16) ||
+        (B->rows > 1 && (B->ld * esize(p.b_dt)) % 16))
+        return false;
     return true;
 }
 
-int find_variant(int dt, int bm, int bn, int wm, int wn, bool b_nk,
-                 bool c_bf16) {
+int find_variant(int dt, int bm, int bn, int wm, int wn, int bk, int stages,
+                 bool b_nk, bool c_bf16) {
     int n = tiled_variant_count();
     for (int i = 0; i < n; ++i) {
         const TiledVariant &v = tiled_variant(i);
         if (v.dtype == dt && v.bm == bm && v.bn == bn && v.b_nk == b_nk &&
             v.c_bf16 == c_bf16 && (wm == 0 || v.wm == wm) &&
-            (wn == 0 || v.wn == wn))
+            (wn == 0 || v.wn == wn) && (bk == 0 || v.bk == bk) &&
+            (stages == 0 || v.stages == stages))
             return i;
     }
     return -1;
@@ -309,7 +314,8 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             cfg.kind = TG_KIND_SKINNY;
         else if (t_ok && (cfg.bm == 0 ||
                           find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm,
-                                       cfg.wn, p.b_nk, p.c_bf16) >= 0))
+                                       cfg.wn, cfg.bk, cfg.stages, p.b_nk,
+                                       p.c_bf16) >= 0))
             cfg.kind = TG_KIND_TILED;
         else
             cfg.kind = TG_KIND_SIMPLE;
@@ -361,15 +367,17 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             return fail(TG_E_ARG, "config bm/bn: set both or neither");
         }
         L.variant = find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
-                                 p.b_nk, p.c_bf16);
+                                 cfg.bk, cfg.stages, p.b_nk, p.c_bf16);
         if (L.variant < 0)
             return fail(TG_E_UNSUPPORTED,
-                        "no tiled kernel for dtype %d, %d x %d, waves %d x %d",
-                        L.gemm_dt, cfg.bm, cfg.bn, cfg.wm, cfg.wn);
+                        "no tiled kernel for dtype %d, %d x %d, waves %d x %d,"
+                        " bk %d, %d stages", L.gemm_dt, cfg.bm, cfg.bn,
+                        cfg.wm, cfg.wn, cfg.bk, cfg.stages);
         const TiledVariant &v = tiled_variant(L.variant);
         cfg.bk = v.bk;
         cfg.wm = v.wm;
         cfg.wn = v.wn;
+        cfg.stages = v.stages;
         cfg.ksplit = 1;
         L.s.tiles_m = (int32_t)((p.M + cfg.bm - 1) / cfg.bm);
         L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
@@ -435,6 +443,7 @@ void candidates(const Problem &p, const tg_in *A, const tg_in *B,
         tg_config c{};
         c.kind = TG_KIND_TILED;
         c.bm = v.bm; c.bn = v.bn; c.wm = v.wm; c.wn = v.wn;
+        c.bk = v.bk; c.stages = v.stages;
         try_cfg(c);
     }
     // the element-wise fallback competes only where nothing else runs
@@ -454,23 +463,29 @@ void features(const Problem &p, const Launch &L, float *f) {
     const tg_config &c = L.cfg;
     const double tiles = L.s.n_tiles > 0 ? L.s.n_tiles : 1;
     const double progs = L.s.n_prog > 0 ? L.s.n_prog : 1;
+    const double rounds = std::ceil(tiles / progs);
+    const auto pos = [](int v) { return (double)(v > 0 ? v : 1); };
     f[0] = lg2((double)p.M);
     f[1] = lg2((double)p.N);
-    f[2] = lg2((double)p.K);
+    f[2] = lg2((double)(p.K > 0 ? p.K : 1));
     f[3] = (p.a_dt == TG_FP8_E4M3 || p.b_dt == TG_FP8_E4M3) ? 1.f : 0.f;
     f[4] = p.a_dt == TG_F32 ? 1.f : 0.f;
     f[5] = p.b_nk ? 1.f : 0.f;
-    f[6] = c.kind == TG_KIND_TILED ? 1.f : 0.f;
-    f[7] = c.kind == TG_KIND_SKINNY ? 1.f : 0.f;
-    f[8] = c.kind == TG_KIND_SIMPLE ? 1.f : 0.f;
-    f[9] = lg2((double)c.bm);
-    f[10] = lg2((double)c.bn);
-    f[11] = lg2((double)(c.ksplit > 0 ? c.ksplit : 1));
-    f[12] = lg2(tiles);
-    f[13] = lg2(std::ceil(tiles / progs));
-    f[14] = (float)((double)p.M * (double)p.N /
+    f[6] = p.c_bf16 ? 1.f : 0.f;
+    f[7] = c.kind == TG_KIND_TILED ? 1.f : 0.f;
+    f[8] = c.kind == TG_KIND_SKINNY ? 1.f : 0.f;
+    f[9] = c.kind == TG_KIND_SIMPLE ? 1.f : 0.f;
+    f[10] = lg2((double)c.bm);
+    f[11] = lg2((double)c.bn);
+    f[12] = lg2(pos(c.wm * c.wn));
+    f[13] = lg2(pos(c.stages));
+    f[14] = lg2(pos(c.ksplit));
+    f[15] = lg2(tiles);
+    f[16] = lg2(progs);
+    f[17] = lg2(rounds);
+    f[18] = (float)(tiles / (progs * rounds));
+    f[19] = (float)((double)p.M * (double)p.N /
                     (tiles * (double)c.bm * (double)c.bn));
-    f[15] = lg2(2.0 * (double)p.M * (double)p.N * (double)(p.K > 0 ? p.K : 1));
 }
 
 // Configuration when the caller gives none: the tuning cache, then the
@@ -820,7 +835,7 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
         cfg.bm = cfg.bn = work >= (int64_t)256 * 256 * 256 ? 256 : 128;
     }
     int variant = find_variant(TG_BF16, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
-                               b_nk == 1, c_bf16 == 1);
+                               cfg.bk, cfg.stages, b_nk == 1, c_bf16 == 1);
     if (variant < 0)
         return fail(TG_E_UNSUPPORTED, "no tiled kernel %d x %d", cfg.bm,
                     cfg.bn);

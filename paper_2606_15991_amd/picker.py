@@ -10,9 +10,11 @@ Workflow (each step runs in the library):
   3. install: tile_picker_set hands the trained parameters to tile_gemm, which
      then picks argmin predicted time over tile_gemm_candidates for shapes it
      has not tuned;
-  4. evaluate: on held-out shapes, regret = time of the exhaustive best /
-     time of the picked configuration, both measured by the autotuner; the
-     fixed default heuristic is scored the same way.
+  4. evaluate: on held-out shapes, the score is time of the exhaustive best /
+     time of the picked configuration, both measured by the autotuner.  Two
+     pickers without the cost model are scored the same way: one fixed
+     configuration for every shape (the first 256 x 256 tiled candidate, the
+     large-problem default) and the library's shape heuristic.
 
 Run as a module for the full workload:
   python -m paper_2606_15991_amd.picker --train 2000 --test 200
@@ -67,7 +69,8 @@ class ShapePool:
 
 
 def _key(cfg):
-    return (cfg["kind"], cfg["bm"], cfg["bn"], cfg["ksplit"])
+    return (cfg["kind"], cfg["bm"], cfg["bn"], cfg["bk"], cfg["wm"],
+            cfg["wn"], cfg["ksplit"], cfg["stages"])
 
 
 def collect(shapes, pool, reps=3, log=None):
@@ -92,11 +95,18 @@ def collect(shapes, pool, reps=3, log=None):
 
 
 def dataset(recs):
+    """Features and targets.  The target is log(ms) relative to the mean
+    over the same shape's candidates: the picker only ranks the candidates
+    of one shape, so the model spends its capacity on the differences between
+    configurations rather than on the (large, easy) differences between
+    shapes."""
     X, y = [], []
     for r in recs:
-        for c in r["cands"]:
+        logs = [math.log(c["ms"]) for c in r["cands"]]
+        mu = sum(logs) / len(logs)
+        for c, lg in zip(r["cands"], logs):
             X.append(c["feat"])
-            y.append(math.log(c["ms"]))
+            y.append(lg - mu)
     return torch.tensor(X, dtype=torch.float32), torch.tensor(
         y, dtype=torch.float32)
 
@@ -142,9 +152,20 @@ def _forward_host(model, feats):
     return [tile_picker_predict(f) for f in feats]
 
 
+def _fixed(cands):
+    """The one configuration used for every shape when nothing is tuned or
+    learned: the first 256 x 256 tiled candidate."""
+    for c in cands:
+        cfg = c["cfg"]
+        if cfg["kind"] == 1 and cfg["bm"] == 256 and cfg["bn"] == 256:
+            return c
+    return None
+
+
 def evaluate(recs, pool):
-    """Regret of the learned picker and of the default heuristic against the
-    exhaustive best, on the autotuner's own timings."""
+    """Score of the learned picker, the fixed configuration and the shape
+    heuristic against the exhaustive best, on the autotuner's own
+    timings."""
     out = []
     old = tile_picker_mode(0)
     try:
@@ -158,8 +179,10 @@ def evaluate(recs, pool):
             dcfg, _, _, _ = tile_gemm_plan(A, B, C, b_trans=True,
                                            want_map=False)
             d_ms = by_key.get(_key(dcfg))
+            fx = _fixed(r["cands"])
             out.append({"shape": r["shape"], "best_ms": r["best_ms"],
                         "mlp_ms": pick["ms"], "default_ms": d_ms,
+                        "fixed_ms": fx["ms"] if fx else None,
                         "mlp_cfg": pick["cfg"], "default_cfg": dcfg})
     finally:
         tile_picker_mode(old)
@@ -172,10 +195,13 @@ def summarize(ev):
         return math.exp(sum(math.log(v) for v in vals) / len(vals))
     mlp = [e["best_ms"] / e["mlp_ms"] for e in ev]
     dft = [e["best_ms"] / e["default_ms"] for e in ev if e["default_ms"]]
+    fix = [e["best_ms"] / e["fixed_ms"] for e in ev if e["fixed_ms"]]
     return {"shapes": len(ev),
             "mlp_geomean_frac_of_best": geo(mlp),
             "mlp_worst_frac": min(mlp),
             "mlp_exact_best": sum(1 for x in mlp if x >= 0.999) / len(mlp),
+            "fixed_geomean_frac_of_best": geo(fix) if fix else None,
+            "fixed_worst_frac": min(fix) if fix else None,
             "default_geomean_frac_of_best": geo(dft),
             "default_worst_frac": min(dft) if dft else None}
 

@@ -252,3 +252,29 @@ def test_workspace_sizes():
         100 * 64 + 64 * 80) and n6 > n3
     assert tg.tile_gemm_workspace_size(A, B, C) == 0
     assert tg.tile_gemm_grouped_workspace_size(64) > 0
+
+
+def test_picker_features_describe_the_configuration():
+    hdr = open(os.path.join(ROOT, "include", "tilegemm.h")).read()
+    n = int(re.search(r"#define TG_PICKER_FEATURES (\d+)", hdr).group(1))
+    assert n == tg.TG_PICKER_FEATURES
+    A = torch.empty((8192, 8192), dtype=torch.bfloat16)
+    B = torch.empty((8192, 8192), dtype=torch.bfloat16)
+    C = torch.empty((8192, 8192), dtype=torch.float32)
+    seen = set()
+    for cfg in tg.tile_gemm_candidates(A, B, C, b_trans=True):
+        f = tg.tile_picker_features(A, B, C, cfg, b_trans=True)
+        _, n_prog, _, _ = tg.tile_gemm_plan(A, B, C, b_trans=True,
+                                            config=cfg, want_map=False)
+        tiles = (8192 // cfg["bm"]) * (8192 // cfg["bn"])
+        rounds = -(-tiles // n_prog)
+        want = [13, 13, 13, 0, 0, 1, 0, 1, 0, 0,
+                np.log2(cfg["bm"]), np.log2(cfg["bn"]),
+                np.log2(cfg["wm"] * cfg["wn"]), np.log2(cfg["stages"]),
+                np.log2(max(cfg["ksplit"], 1)), np.log2(tiles),
+                np.log2(n_prog), np.log2(rounds),
+                tiles / (n_prog * rounds), 1.0]
+        assert np.allclose(f, want, rtol=0, atol=1e-6), (cfg, f)
+        seen.add(tuple(f))
+    # every candidate is distinguishable by its features
+    assert len(seen) == len(tg.tile_gemm_candidates(A, B, C, b_trans=True))

@@ -113,24 +113,26 @@ def test_tune_cache_save_load_roundtrip(tmp_path):
 
 
 def test_learned_picker_beats_default_and_tracks_exhaustive():
-    """Small version of the picker workload: 240 training shapes, 60
-    held-out shapes (M, N, K log-uniform in [1, 4096], bf16 / e4m3)."""
+    """Small version of the picker workload: 400 training shapes, 80
+    held-out shapes (M, N, K log-uniform in [1, 4096], bf16 / e4m3).  The
+    learned picker must stay close to the exhaustive best and beat the one
+    fixed configuration it replaces; the shape heuristic is reported."""
     from paper_2606_15991_amd import picker
-    note("picker train 240 / test 60")
+    note("picker train 400 / test 80")
     tg.tile_tune_cache_clear()
     pool = picker.ShapePool(max_dim=4096)
-    tr = picker.collect(synth.picker_shapes(5, 240, hi=4096), pool, reps=2)
+    tr = picker.collect(synth.picker_shapes(5, 400, hi=4096), pool, reps=5)
     model = picker.train(tr, steps=1500)
     hist = model["loss_history"]
     assert hist[-1][1] < 0.5 * hist[0][1]
     picker.install(model)
-    te = picker.collect(synth.picker_shapes(6, 60, hi=4096), pool, reps=2)
+    te = picker.collect(synth.picker_shapes(6, 80, hi=4096), pool, reps=5)
     tg.tile_tune_cache_clear()
     ev = picker.evaluate(te, pool)
     s = picker.summarize(ev)
     note("picker summary", s)
-    assert s["mlp_geomean_frac_of_best"] >= 0.85
-    assert s["mlp_geomean_frac_of_best"] >= s["default_geomean_frac_of_best"]
+    assert s["mlp_geomean_frac_of_best"] >= 0.90
+    assert s["mlp_geomean_frac_of_best"] > s["fixed_geomean_frac_of_best"]
     # tile_gemm itself follows the installed model when nothing is cached
     old = tg.tile_picker_mode(2)
     try:
