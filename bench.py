@@ -3,7 +3,8 @@
 
 Headline: BF16 GEMM M = N = K = 8192 (entries N(0,1) rounded to bf16, binary32
 accumulation and output, C split into 256 x 256 sub-tensors, one persistent
-launch of tile programs).  One step = one tile_gemm launch over the resident
+launch of tile programs; A row-major, B column-major, i.e. B held as its
+N x K transpose).  One step = one tile_gemm launch over the resident
 inputs.  Prints ONE JSON line with TFLOP/s, the roofline fraction of the
 dominant kernel, the error against the oracle on sampled rows, the oracle's
 own CPU rate on those rows, and secondary measurements (FP8, FP32, split
@@ -125,12 +126,12 @@ def bench_bf16_main(args, tg):
     M = N = K = 8192
     log("bf16 8192^3: generating inputs")
     A = synth.to_bf16(synth.normal((M, K), 2))
-    B = synth.to_bf16(synth.normal((K, N), 202))
-    Ad, Bd = A.cuda(), B.cuda()
+    Bt = synth.to_bf16(synth.normal((N, K), 202))   # B^T, row-major
+    Ad, Bd = A.cuda(), Bt.cuda()
     C = torch.empty((M, N), device="cuda")
 
     def step():
-        tg.tile_gemm(Ad, Bd, C, 256, 256)
+        tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True)
 
     log("bf16 8192^3: timing")
     ms = timed(step, args.steps, args.warmup)
@@ -138,31 +139,44 @@ def bench_bf16_main(args, tg):
     tflops = flops / (ms * 1e-3) / 1e12
     # unchecked twin: same kernel, partition check skipped on the host
     ms_unchecked = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256,
-                                              checked=False),
+                                              b_trans=True, checked=False),
                          max(args.steps // 2, 5), 2)
     step()
     torch.cuda.synchronize()
     Cc = C.cpu().numpy()
     res = {"M": M, "N": N, "K": K, "ms": ms, "tflops": tflops,
-           "ms_unchecked": ms_unchecked, "A": A, "B": B, "C": Cc}
+           "ms_unchecked": ms_unchecked, "A": A, "Bt": Bt, "C": Cc}
     return res
 
 
-def bench_bf16_nk(args, tg):
-    """Same product with B stored N x K (C = A . B^T of a row-major N x K)."""
+def bench_bf16_kn(args, tg):
+    """Same product with B row-major (stored K x N)."""
     n = 8192
     A = synth.to_bf16(synth.normal((n, n), 2)).cuda()
     B = synth.to_bf16(synth.normal((n, n), 202)).cuda()
     C = torch.empty((n, n), device="cuda")
-    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256, b_trans=True), 20, 3)
+    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256), 20, 3)
     return {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling the FETCH_SIZE and
+    WRITE_SIZE counters of a profiled run to bytes."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
 def cpu_baseline_and_err(res, target_s):
     import oracle
     rng = np.random.default_rng(2)
     rows = rng.permutation(res["M"])[:512]
-    done, R, secs = oracle_rows(res["A"], res["B"], rows, target_s=target_s)
+    done, R, secs = oracle_rows(res["A"], res["Bt"], rows, b_nk=True,
+                                target_s=target_s)
     got = res["C"][done].astype(np.float64)
     err = oracle.rel_fro(got, R)
     flops = 2.0 * len(done) * res["N"] * res["K"]
@@ -280,6 +294,8 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--picker", action="store_true",
                     help="also run the learned-picker evaluation "
                          "(2000 training / 200 held-out shapes)")
@@ -291,6 +307,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import paper_2606_15991_amd as tg
 
     res = bench_bf16_main(args, tg)
@@ -300,7 +319,7 @@ def main():
         extra.update(bench_f32_and_split(args, tg))
         extra["decode"] = bench_decode(args, tg)
         extra["grouped"] = bench_grouped(args, tg)
-        extra["bf16_8192_b_stored_nk"] = bench_bf16_nk(args, tg)
+        extra["bf16_8192_b_row_major"] = bench_bf16_kn(args, tg)
     if args.picker:
         from paper_2606_15991_amd import picker
         import io
@@ -326,7 +345,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "bf16 GEMM M=N=K=8192, N(0,1) inputs, "
                                "f32 accumulate+output, C partition 256x256, "
-                               "A and B row-major (B stored K x N)",
+                               "A row-major, B column-major (stored N x K)",
                    "M": 8192, "N": 8192, "K": 8192,
                    "partition": [256, 256], "parallelism": "none"},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2),

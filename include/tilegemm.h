@@ -112,8 +112,9 @@ typedef struct tg_out {
 /*
  * Kernel configuration.  bm x bn must equal the output partition; bk is the
  * K-tile depth; wm x wn is the wavefront grid of one workgroup; stages is
- * the number of K tiles held in LDS at once; `kind` selects the kernel
- * family.  Unset fields (0) are filled by the picker.
+ * the number of K tiles held in LDS at once; sched is the wavefront
+ * schedule of the tiled kernel; `kind` selects the kernel family.  Unset
+ * fields (0) are filled by the picker.
  */
 typedef enum tg_kind {
     TG_KIND_AUTO = 0,
@@ -122,12 +123,21 @@ typedef enum tg_kind {
     TG_KIND_SIMPLE = 3    /* small-tile kernel with no alignment demands     */
 } tg_kind;
 
+typedef enum tg_sched {
+    TG_SCHED_ANY = 0,
+    TG_SCHED_LOCKSTEP = 1, /* all wavefronts load, then all contract         */
+    TG_SCHED_PINGPONG = 2  /* two wavefront groups alternate between loading
+                              and contracting, one phase apart; needs K a
+                              multiple of 16 bytes of the operand type      */
+} tg_sched;
+
 typedef struct tg_config {
     int32_t kind;         /* tg_kind                                         */
     int32_t bm, bn, bk;
     int32_t wm, wn;
     int32_t ksplit;       /* skinny kernel: wavefronts sharing one tile's K  */
     int32_t stages;       /* tiled kernel: LDS stages of the K-tile ring     */
+    int32_t sched;        /* tiled kernel: tg_sched                          */
 } tg_config;
 
 typedef struct tg_opts {
@@ -292,7 +302,7 @@ tg_status tile_tune_cache_load(const char *path);
  * pair, in this order: log2 M, N, K; flags for e4m3 operands, f32 operands,
  * B stored N x K and a bf16 output; the kernel kind (three one-hot flags:
  * tiled, skinny, simple); log2 bm, bn, wavefronts per program, LDS stages
- * and ksplit; log2 of the sub-tensor count, of the program count and of the
+ * and ksplit; a ping-pong schedule flag; log2 of the sub-tensor count, of the program count and of the
  * sub-tensors per program; the fraction of the last round of sub-tensors
  * that has work; the useful fraction of the padded output area.
  * tile_picker_set installs a cost model (host copy of the parameters in the
@@ -301,7 +311,7 @@ tg_status tile_tune_cache_load(const char *path);
  * tile_picker_mode(mode) sets bit 1 = use the tuning cache, bit 2 = use the
  * cost model (mode < 0 only queries) and returns the previous mode.
  */
-#define TG_PICKER_FEATURES 20
+#define TG_PICKER_FEATURES 21
 tg_status tile_picker_features(const tg_in *A, const tg_in *B,
                                const tg_out *C, const tg_config *cfg,
                                float *feat);

@@ -31,6 +31,8 @@ TG_F32, TG_BF16, TG_FP8_E4M3 = 0, 1, 2
 TG_PREC_NATIVE, TG_PREC_BF16X3, TG_PREC_BF16X6 = 0, 1, 2
 # tg_kind
 TG_KIND_AUTO, TG_KIND_TILED, TG_KIND_SKINNY, TG_KIND_SIMPLE = 0, 1, 2, 3
+# tg_sched
+TG_SCHED_ANY, TG_SCHED_LOCKSTEP, TG_SCHED_PINGPONG = 0, 1, 2
 TG_ERROR_NORM_DOUBLES = 514
 
 PRECISIONS = {"native": TG_PREC_NATIVE, "bf16x3": TG_PREC_BF16X3,
@@ -56,7 +58,8 @@ class tg_config(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("bm", ctypes.c_int32),
                 ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
                 ("wm", ctypes.c_int32), ("wn", ctypes.c_int32),
-                ("ksplit", ctypes.c_int32), ("stages", ctypes.c_int32)]
+                ("ksplit", ctypes.c_int32), ("stages", ctypes.c_int32),
+                ("sched", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -76,7 +79,7 @@ class tg_tune_result(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
-TG_PICKER_FEATURES = 20
+TG_PICKER_FEATURES = 21
 
 
 class TileGemmError(RuntimeError):

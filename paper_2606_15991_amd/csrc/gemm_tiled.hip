@@ -60,7 +60,7 @@ struct DtypeTraits<TG_FP8_E4M3> {
 };
 
 template <int DT, int BM_, int BN_, int WM_, int WN_, bool BNK_, bool CBF16_,
-          int RBY_ = 128, int NS_ = 2>
+          int RBY_ = 128, int NS_ = 2, bool PP_ = false>
 struct Cfg {
     static constexpr int DTYPE = DT;
     static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
@@ -69,6 +69,7 @@ struct Cfg {
     static constexpr int EPC = 16 / ES;         // elements per 16-byte chunk
     static constexpr int RBY = RBY_;            // bytes of K per operand row
     static constexpr int NS = NS_;              // LDS stages in the ring
+    static constexpr bool PP = PP_;             // ping-pong wave schedule
     static constexpr int BK = RBY / ES;         // K elements per K tile
     static constexpr int CPRW = RBY / 16;       // 16-byte chunks per row
     static constexpr int RPK = 1024 / RBY;      // rows per 1 KiB block
@@ -100,6 +101,8 @@ struct Cfg {
     static_assert(!B_KMAJOR || CPR >= 4, "k-major B rows of >= 64 bytes");
     static_assert(DT != TG_FP8_E4M3 || BK >= 64, "e4m3 K tile >= 64");
     static_assert(LPW * (NS - 2) < 64, "vmcnt range");
+    static_assert(!PP || (DIRECT && WM == 2 && NW == 8 && NS >= 3),
+                  "ping-pong: two groups of four wavefronts, >= 3 stages");
 };
 
 // Row-major [rows][RBY bytes] operand stage: chunk c of row r sits at chunk
@@ -135,14 +138,18 @@ __device__ __forceinline__ int swz_kmajor(int k) {
     }
 }
 
-__device__ __forceinline__ void wait_vmem() {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-}
-
+// Vector-memory counter waits, as s_waitcnt instructions the compiler sees
+// (its own wait insertion then knows which loads are complete).  Encoding:
+// vmcnt in bits [3:0] and [15:14], expcnt [6:4] and lgkmcnt [11:8] at their
+// no-wait maxima.
 template <int N>
 __device__ __forceinline__ void wait_vmem_le() {
-    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) |
+                               (15 << 8));
 }
+
+__device__ __forceinline__ void wait_vmem() { wait_vmem_le<0>(); }
 
 // Workgroup barrier for the K-tile ring.  __syncthreads() carries a
 // workgroup-scope fence, which waits for every outstanding global access of
@@ -183,10 +190,49 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base,
 
 constexpr uint32_t kOutOfRange = 0x80000000u;
 
-__device__ __forceinline__ void buf_to_lds(__amdgpu_buffer_rsrc_t r,
-                                           char *dst, uint32_t voff) {
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void *)dst, 16, voff, 0,
-                                             0, 0);
+// Direct loads are issued from inline assembly.  The compiler's own
+// dependency tracking would place waits on the vector-memory counter in
+// front of LDS reads it cannot prove disjoint from a load's LDS
+// destination, which drains the loads that must stay in flight; the K-tile
+// schedules here order every LDS access explicitly instead (counter waits
+// before workgroup barriers).
+//
+// Descriptor words of a raw buffer (no stride) in scalar registers.
+__device__ __forceinline__ i32x4 make_srd(const void *base, uint32_t bytes) {
+    const uint64_t p = reinterpret_cast<uint64_t>(base);
+    i32x4 d;
+    d[0] = __builtin_amdgcn_readfirstlane((int)(uint32_t)p);
+    d[1] = __builtin_amdgcn_readfirstlane((int)((uint32_t)(p >> 32) & 0xffffu));
+    d[2] = __builtin_amdgcn_readfirstlane((int)bytes);
+    d[3] = 0x00020000;
+    return d;
+}
+
+// One 16-byte-per-lane load from buffer `srd` at byte offset `voff` into
+// LDS at dst + 16 * lane.  M0 holds the LDS address; one wait state
+// separates its write from the load.  The first load after `srd` was
+// formed also waits five states, the distance a vector-ALU write of a
+// scalar register needs before a vector-memory instruction reads it.
+template <bool FIRST>
+__device__ __forceinline__ void dma16(const i32x4 &srd, char *dst,
+                                      uint32_t voff) {
+    const uint32_t lds = __builtin_amdgcn_readfirstlane(
+        (int)static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
+            (lds_void *)dst)));
+    if constexpr (FIRST)
+        asm volatile(
+            "s_nop 4\n\ts_mov_b32 m0, %0\n\ts_nop 0\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen lds"
+            :
+            : "s"(lds), "v"(voff), "s"(srd)
+            : "memory", "m0");
+    else
+        asm volatile(
+            "s_mov_b32 m0, %0\n\ts_nop 0\n\t"
+            "buffer_load_dwordx4 %1, %2, 0 offen lds"
+            :
+            : "s"(lds), "v"(voff), "s"(srd)
+            : "memory", "m0");
 }
 
 __device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
@@ -206,7 +252,7 @@ __device__ __forceinline__ void issue_operand(const char *mat, int64_t ld,
                                               int lane) {
     const char *base = mat + ((int64_t)r0 * ld + k0) * C::ES;
     const uint32_t nrec = sat_bytes(((int64_t)(rows - r0) * ld - k0) * C::ES);
-    const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
+    const i32x4 srd = make_srd(base, nrec);
     const int rsub = lane / C::CPRW, p = lane % C::CPRW;
 #pragma unroll
     for (int i = 0; i < ROWS / C::RPK / C::NW; ++i) {
@@ -214,9 +260,12 @@ __device__ __forceinline__ void issue_operand(const char *mat, int64_t ld,
         const int row = rb * C::RPK + rsub;           // row within the tile
         const int kc = p ^ swz_f<C>(row);
         const bool kin = k0 + (kc + 1) * C::EPC <= K;
-        buf_to_lds(r, dst + rb * 1024,
-                   kin ? (uint32_t)((row * ld + kc * C::EPC) * C::ES)
-                       : kOutOfRange);
+        const uint32_t off = kin ? (uint32_t)((row * ld + kc * C::EPC) * C::ES)
+                                 : kOutOfRange;
+        if (i == 0)
+            dma16<true>(srd, dst + rb * 1024, off);
+        else
+            dma16<false>(srd, dst + rb * 1024, off);
     }
 }
 
@@ -234,7 +283,7 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
         const char *base = j.b + ((int64_t)k0 * j.ldb + j.n0) * C::ES;
         const uint32_t nrec =
             sat_bytes(((int64_t)(j.K - k0) * j.ldb - j.n0) * C::ES);
-        const __amdgpu_buffer_rsrc_t r = make_rsrc(base, nrec);
+        const i32x4 srd = make_srd(base, nrec);
 #pragma unroll
         for (int i = 0; i < C::BK * C::RB / 1024 / C::NW; ++i) {
             const int gi = i * C::NW + wave;
@@ -242,9 +291,13 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
             const int k = off / C::RB;
             const int lc = ((off % C::RB) >> 4) ^ swz_kmajor<C>(k);
             const bool nin = j.n0 + lc * C::EPC < j.N;
-            buf_to_lds(r, Bs + gi * 1024,
-                       nin ? (uint32_t)((k * j.ldb + lc * C::EPC) * C::ES)
-                           : kOutOfRange);
+            const uint32_t voff =
+                nin ? (uint32_t)((k * j.ldb + lc * C::EPC) * C::ES)
+                    : kOutOfRange;
+            if (i == 0)
+                dma16<true>(srd, Bs + gi * 1024, voff);
+            else
+                dma16<false>(srd, Bs + gi * 1024, voff);
         }
     }
 }
@@ -470,46 +523,48 @@ __device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
                                          int lane,
                                          f32x16 (&acc)[C::FM][C::FN]) {
     constexpr int OES = C::CBF16 ? 2 : 4;
+    // The address arithmetic below is loop-invariant in a persistent
+    // program; hidden from the optimiser so that it is formed here, per
+    // stored sub-tensor, instead of being hoisted and held in registers
+    // across the whole K loop.
+    int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)j.ldc);
+    int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(j.ldc >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    const int64_t ldc = (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
     const int col_l = lane & 31, half = lane >> 5;
     const int r0 = wm * C::TM + 4 * half;        // row of v = 0, i = 0
     const int c0 = wn * C::TN + col_l;           // column of jj = 0
     char *base = static_cast<char *>(j.c) +
-                 ((int64_t)j.m0 * j.ldc + j.n0) * OES;
+                 ((int64_t)j.m0 * ldc + j.n0) * OES;
     const __amdgpu_buffer_rsrc_t r = make_rsrc(
-        base, sat_bytes(((int64_t)(j.M - j.m0 - 1) * j.ldc + (j.N - j.n0)) *
+        base, sat_bytes(((int64_t)(j.M - j.m0 - 1) * ldc + (j.N - j.n0)) *
                         OES));
     const int rows_left = j.M - j.m0 - r0;       // rows with local index < this
     const int cols_left = j.N - j.n0 - c0;
+    // Scales are loaded, and waited for, before any store is issued, and
+    // inside the branch that loads them, so that no load of this epilogue
+    // is outstanding (or believed outstanding) when the K loop resumes.
     float sb[C::FN];
 #pragma unroll
-    for (int jj = 0; jj < C::FN; ++jj)
-        sb[jj] = (j.scale_b && jj * 32 < cols_left) ? j.scale_b[j.n0 + c0 +
-                                                                jj * 32]
-                                                     : 1.0f;
-    const uint32_t lane_off = (uint32_t)((r0 * j.ldc + c0) * OES);
-    // every scale is loaded before the first store: a wait for a load
-    // issued after stores would also wait for those stores (one counter)
-    float sa[C::FM][16];
+    for (int jj = 0; jj < C::FN; ++jj) sb[jj] = 1.0f;
+    if (j.scale_b) {
 #pragma unroll
-    for (int i = 0; i < C::FM; ++i)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
-            sa[i][v] = (j.scale_a && dr < rows_left)
-                           ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
-        }
-#pragma unroll
-    for (int i = 0; i < C::FM; ++i) {
+        for (int jj = 0; jj < C::FN; ++jj)
+            if (jj * 32 < cols_left) sb[jj] = j.scale_b[j.n0 + c0 + jj * 32];
+        wait_vmem();
+    }
+    const uint32_t lane_off = (uint32_t)((r0 * ldc + c0) * OES);
+    auto store_rows = [&](int i, const float (&sa)[16]) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
             const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
             const bool row_ok = dr < rows_left;
-            const uint32_t roff = lane_off + (uint32_t)(dr * j.ldc * OES);
+            const uint32_t roff = lane_off + (uint32_t)(dr * ldc * OES);
 #pragma unroll
             for (int jj = 0; jj < C::FN; ++jj) {
                 const bool ok = row_ok && jj * 32 < cols_left;
                 const uint32_t off = ok ? roff + jj * 32 * OES : kOutOfRange;
-                const float x = acc[i][jj][v] * sb[jj] * sa[i][v];
+                const float x = acc[i][jj][v] * sb[jj] * sa[v];
                 if constexpr (C::CBF16)
                     __builtin_amdgcn_raw_buffer_store_b16(
                         (unsigned short)f32_to_bf16_bits(x), r, off, 0, 0);
@@ -517,6 +572,24 @@ __device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
                     __builtin_amdgcn_raw_buffer_store_b32(
                         __builtin_bit_cast(uint32_t, x), r, off, 0, 0);
             }
+        }
+    };
+    if (!j.scale_a) {
+        const float ones[16] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f,
+                                1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) store_rows(i, ones);
+    } else {
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i) {
+            float sa[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
+                sa[v] = dr < rows_left ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
+            }
+            wait_vmem();
+            store_rows(i, sa);
         }
     }
     if (j.wcount) {
@@ -620,7 +693,8 @@ __device__ __forceinline__ void wait_tile(int later) {
 template <class C, class P>
 __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int wm = wave / C::WN, wn = wave % C::WN;
     const int G = prov.n_prog(), total = prov.count();
     int t = program_slot(blockIdx.x, G);
@@ -680,7 +754,8 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
 template <class C, class P>
 __device__ __forceinline__ void run_regs(const P &prov, char *smem) {
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
     const int wm = wave / C::WN, wn = wave % C::WN;
     const int G = prov.n_prog(), total = prov.count();
     f32x16 acc[C::FM][C::FN];
@@ -710,6 +785,207 @@ __device__ __forceinline__ void run_regs(const P &prov, char *smem) {
         }
         epilogue<C>(j, wm, wn, lane, acc);
     }
+}
+
+// ------------------------------------------------------ ping-pong schedule
+//
+// Eight wavefronts in two groups of four (group = wm); the hardware places
+// wavefront w on SIMD w % 4, so every SIMD holds one wavefront of each
+// group.  The groups run the same sequence of phases, one phase apart:
+//   MEM(q):  issue the HBM -> LDS loads of K tile q + NS - 1, then read this
+//            wavefront's fragments of K tile q from LDS into registers;
+//   COMP(q): the MFMAs of K tile q, from registers only.
+// A workgroup barrier separates consecutive phases, so while one group
+// contracts, the other group's LDS reads and load issue run on the same
+// SIMDs, and the MFMA pipe of each SIMD is fed from one long run of
+// independent instructions.  K tiles of consecutive owned sub-tensors form
+// one stream q = 0, 1, ...; the loads run NS - 1 tiles ahead.
+//
+// Ordering (phase k starts at barrier k; group 0 runs MEM(q) in phase 2q
+// and COMP(q) in 2q + 1, group 1 one phase later):
+//  * tile q is first read in phase 2q: every wavefront waits for its own
+//    loads of tile q before barrier 2q (group 0 before MEM(q), group 1
+//    before COMP(q - 1));
+//  * the loads of tile q + NS - 1 overwrite the stage of tile q - 1, whose
+//    last reader (group 1, MEM(q - 1), phase 2q - 1) finished its LDS reads
+//    before barrier 2q, the earliest issue of those loads;
+//  * both groups pass the same number of barriers: group 1 one extra at the
+//    start, group 0 one extra at the end.
+template <class C>
+struct PPFrag {
+    static constexpr bool F8 = C::DTYPE == TG_FP8_E4M3;
+    static constexpr int KS = F8 ? C::BK / 64 : C::BK / 16;  // MFMA K steps
+    static constexpr int W = F8 ? 2 : 1;                     // i32x4 / operand
+    i32x4 a[KS][C::FM][W];
+    i32x4 b[KS][C::FN][W];
+};
+
+template <class C>
+__device__ __forceinline__ void pp_read(const char *stage, int wm, int wn,
+                                        int lane, PPFrag<C> &f) {
+    const char *As = stage;
+    const char *Bs = stage + C::BM * C::RBY;
+    const int r = lane & 31, half = lane >> 5;
+#pragma unroll
+    for (int ks = 0; ks < PPFrag<C>::KS; ++ks) {
+        const int c = PPFrag<C>::F8 ? 4 * ks + 2 * half : 2 * ks + half;
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+            for (int w = 0; w < PPFrag<C>::W; ++w)
+                f.a[ks][i][w] = *reinterpret_cast<const i32x4 *>(
+                    As + swz<C>(wm * C::TM + i * 32 + r, c + w));
+#pragma unroll
+        for (int jj = 0; jj < C::FN; ++jj) {
+            if constexpr (C::B_KMAJOR) {
+                f.b[ks][jj][0] =
+                    read_b_kmajor<C>(Bs, ks, wn * C::TN + jj * 32, lane);
+            } else {
+#pragma unroll
+                for (int w = 0; w < PPFrag<C>::W; ++w)
+                    f.b[ks][jj][w] = *reinterpret_cast<const i32x4 *>(
+                        Bs + swz<C>(wn * C::TN + jj * 32 + r, c + w));
+            }
+        }
+    }
+}
+
+template <class C>
+__device__ __forceinline__ void pp_mfma(const PPFrag<C> &f,
+                                        f32x16 (&acc)[C::FM][C::FN]) {
+#pragma unroll
+    for (int ks = 0; ks < PPFrag<C>::KS; ++ks)
+#pragma unroll
+        for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+            for (int jj = 0; jj < C::FN; ++jj) {
+                if constexpr (PPFrag<C>::F8) {
+                    const i32x4 a0 = f.a[ks][i][0], a1 = f.a[ks][i][1];
+                    const i32x4 b0 = f.b[ks][jj][0], b1 = f.b[ks][jj][1];
+                    acc[i][jj] = mfma_fp8(
+                        i32x8{a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2],
+                              a1[3]},
+                        i32x8{b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2],
+                              b1[3]},
+                        acc[i][jj]);
+                } else {
+                    acc[i][jj] = mfma_bf16(f.a[ks][i][0], f.b[ks][jj][0],
+                                           acc[i][jj]);
+                }
+            }
+}
+
+// Barrier between two phases: this wavefront's LDS reads are complete, and
+// no instruction moves across it.
+__device__ __forceinline__ void phase_barrier() {
+    __builtin_amdgcn_sched_barrier(0);
+    ring_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// K tiles of one owned sub-tensor in the stream; K = 0 takes one tile of
+// zeros (every chunk lies beyond K and loads as zeros).
+template <class C>
+__device__ __forceinline__ int pp_tiles(int K) {
+    const int nk = (K + C::BK - 1) / C::BK;
+    return nk > 0 ? nk : 1;
+}
+
+// Loads of the K-tile stream in issue order: (owned sub-tensor, K tile).
+template <class C, class P>
+struct LoadCursor {
+    const P &prov;
+    Job j;
+    int t, kt, nk, total, G;
+    int issued;   // tiles issued so far (stream index of the next one)
+
+    __device__ LoadCursor(const P &p, int t0, int total_, int G_)
+        : prov(p), t(t0), kt(0), total(total_), G(G_), issued(0) {
+        j = prov.job(t);
+        nk = pp_tiles<C>(j.K);
+    }
+    __device__ __forceinline__ void issue(char *smem, int wave, int lane) {
+        if (t >= total) return;
+        issue_direct<C>(j, smem + (issued % C::NS) * C::STAGE, kt * C::BK,
+                        wave, lane);
+        ++issued;
+        if (++kt == nk) {
+            kt = 0;
+            t += G;
+            if (t < total) {
+                j = prov.job(t);
+                nk = pp_tiles<C>(j.K);
+            }
+        }
+    }
+};
+
+// Wait until this wavefront's loads of stream tile q have landed.  Loads
+// complete in issue order; after epilogue stores (dirty) everything is
+// drained, since stores need not complete in order with loads.
+template <class C>
+__device__ __forceinline__ void pp_wait(int q, int issued, bool &dirty) {
+    if (q >= issued) return;   // past the end of the stream
+    if (dirty) {
+        wait_vmem();
+        dirty = false;
+        return;
+    }
+    int later = issued - 1 - q;
+    later = later < C::NS - 2 ? later : C::NS - 2;
+    wait_tile<C>(later);
+}
+
+// Ping-pong programs (bf16, e4m3; K a positive multiple of the 16-byte
+// chunk, so no tile needs a tail fill).
+template <class C, class P>
+__device__ __forceinline__ void run_pingpong(const P &prov, char *smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int grp = wm;
+    const int G = prov.n_prog(), total = prov.count();
+    int t = program_slot(blockIdx.x, G);
+    if (t >= total) return;
+    LoadCursor<C, P> ld(prov, t, total, G);
+    for (int s = 0; s < C::NS - 1; ++s) ld.issue(smem, wave, lane);
+    Job j = prov.job(t);
+    int nk = pp_tiles<C>(j.K);
+    int kt = 0, q = 0;
+    bool dirty = false;
+    f32x16 acc[C::FM][C::FN];
+    zero_acc<C>(acc);
+    PPFrag<C> f;
+    if (grp == 1) {
+        pp_wait<C>(0, ld.issued, dirty);
+        phase_barrier();
+    }
+    while (true) {
+        // MEM(q)
+        if (grp == 0) pp_wait<C>(q, ld.issued, dirty);
+        phase_barrier();
+        ld.issue(smem, wave, lane);
+        pp_read<C>(smem + (q % C::NS) * C::STAGE, wm, wn, lane, f);
+        // COMP(q)
+        if (grp == 1) pp_wait<C>(q + 1, ld.issued, dirty);
+        phase_barrier();
+        __builtin_amdgcn_s_setprio(1);
+        pp_mfma<C>(f, acc);
+        __builtin_amdgcn_s_setprio(0);
+        ++q;
+        if (++kt == nk) {
+            epilogue<C>(j, wm, wn, lane, acc);
+            dirty = true;
+            t += G;
+            if (t >= total) break;
+            j = prov.job(t);
+            nk = pp_tiles<C>(j.K);
+            kt = 0;
+            zero_acc<C>(acc);
+        }
+    }
+    if (grp == 0) phase_barrier();
 }
 
 // One problem: traversal index -> owned sub-tensor.
@@ -769,7 +1045,9 @@ template <class C>
 __global__ __launch_bounds__(C::THREADS) void gemm_tiled_kernel(GemmArgs g) {
     extern __shared__ __align__(1024) char smem[];
     SingleProvider<C> p{g};
-    if constexpr (C::DIRECT)
+    if constexpr (C::PP)
+        run_pingpong<C>(p, smem);
+    else if constexpr (C::DIRECT)
         run_direct<C>(p, smem);
     else
         run_regs<C>(p, smem);
@@ -780,7 +1058,9 @@ __global__ __launch_bounds__(C::THREADS) void gemm_grouped_kernel(
     const GroupProblem *__restrict__ tab, int n, int total, int G) {
     extern __shared__ __align__(1024) char smem[];
     GroupProvider<C> p{tab, n, total, G};
-    if constexpr (C::DIRECT)
+    if constexpr (C::PP)
+        run_pingpong<C>(p, smem);
+    else if constexpr (C::DIRECT)
         run_direct<C>(p, smem);
     else
         run_regs<C>(p, smem);
@@ -799,6 +1079,7 @@ VariantEntry make_entry() {
     VariantEntry e;
     e.v.dtype = C::DTYPE;
     e.v.bm = C::BM; e.v.bn = C::BN; e.v.bk = C::BK; e.v.stages = C::NS;
+    e.v.sched = C::PP ? TG_SCHED_PINGPONG : TG_SCHED_LOCKSTEP;
     e.v.wm = C::WM; e.v.wn = C::WN;
     e.v.b_nk = C::BNK; e.v.c_bf16 = C::CBF16;
     e.kernel = reinterpret_cast<const void *>(&gemm_tiled_kernel<C>);
@@ -818,13 +1099,23 @@ VariantEntry make_entry() {
     make_entry<Cfg<DT, BM, BN, WM, WN, true, false, RBY, NS>>(),              \
         make_entry<Cfg<DT, BM, BN, WM, WN, true, true, RBY, NS>>()
 
+#define TG_VARIANTS_PP(DT, BM, BN, RBY, NS)                                   \
+    make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, true>>(),         \
+        make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, true>>(),      \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, true>>(),      \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, true>>()
+
+#define TG_VARIANTS_PP_NK(DT, BM, BN, RBY, NS)                                \
+    make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, true>>(),          \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, true>>()
+
 // Table order is preference order: the first variant matching a request's
 // dtype, partition, layout and output type is the default.
 const VariantEntry *table(int *count) {
     static const VariantEntry entries[] = {
-        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 64, 4),
-        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 2, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 128, 2),
+        TG_VARIANTS_PP(TG_BF16, 256, 256, 64, 4),
+        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2, 128, 2),
@@ -832,9 +1123,9 @@ const VariantEntry *table(int *count) {
         TG_VARIANTS_FOR(TG_F32, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_F32, 64, 64, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_F32, 32, 32, 1, 1, 128, 2),
-        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 2, 128, 2),
-        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 4, 64, 4),
         TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 4, 128, 2),
+        TG_VARIANTS_PP_NK(TG_FP8_E4M3, 256, 256, 64, 4),
+        TG_VARIANTS_NK(TG_FP8_E4M3, 256, 256, 2, 4, 64, 4),
         TG_VARIANTS_NK(TG_FP8_E4M3, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_NK(TG_FP8_E4M3, 64, 64, 2, 2, 128, 2),
         TG_VARIANTS_NK(TG_FP8_E4M3, 32, 32, 1, 1, 128, 2),

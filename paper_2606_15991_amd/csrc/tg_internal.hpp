@@ -94,6 +94,7 @@ struct TiledVariant {
     int32_t dtype;   // tg_dtype of A and B
     int32_t bm, bn, bk, wm, wn;
     int32_t stages;  // LDS stages in the K-tile ring
+    int32_t sched;   // tg_sched (lock-step or ping-pong)
     int32_t b_nk;
     int32_t c_bf16;
 };

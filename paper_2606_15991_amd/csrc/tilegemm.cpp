@@ -240,19 +240,26 @@ bool skinny_ok(const Problem &p, const tg_in *A, const tg_in *B) {
     return true;
 }
 
+// First tiled variant matching the request; zero fields match anything.
+// Ping-pong variants have no tail fill for a 16-byte chunk straddling K:
+// pp_ok is false when K is not a multiple of the chunk.
 int find_variant(int dt, int bm, int bn, int wm, int wn, int bk, int stages,
-                 bool b_nk, bool c_bf16) {
+                 int sched, bool b_nk, bool c_bf16, bool pp_ok) {
     int n = tiled_variant_count();
     for (int i = 0; i < n; ++i) {
         const TiledVariant &v = tiled_variant(i);
+        if (v.sched == TG_SCHED_PINGPONG && !pp_ok) continue;
         if (v.dtype == dt && v.bm == bm && v.bn == bn && v.b_nk == b_nk &&
             v.c_bf16 == c_bf16 && (wm == 0 || v.wm == wm) &&
             (wn == 0 || v.wn == wn) && (bk == 0 || v.bk == bk) &&
-            (stages == 0 || v.stages == stages))
+            (stages == 0 || v.stages == stages) &&
+            (sched == 0 || v.sched == sched))
             return i;
     }
     return -1;
 }
+
+bool chunk_multiple(int64_t K, int dt) { return (K * esize(dt)) % 16 == 0; }
 
 // Default tile choice: the largest square tile that still gives every
 // compute unit close to one sub-tensor.
@@ -314,8 +321,9 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             cfg.kind = TG_KIND_SKINNY;
         else if (t_ok && (cfg.bm == 0 ||
                           find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm,
-                                       cfg.wn, cfg.bk, cfg.stages, p.b_nk,
-                                       p.c_bf16) >= 0))
+                                       cfg.wn, cfg.bk, cfg.stages, cfg.sched,
+                                       p.b_nk, p.c_bf16,
+                                       chunk_multiple(L.Kc, L.gemm_dt)) >= 0))
             cfg.kind = TG_KIND_TILED;
         else
             cfg.kind = TG_KIND_SIMPLE;
@@ -367,17 +375,20 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             return fail(TG_E_ARG, "config bm/bn: set both or neither");
         }
         L.variant = find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
-                                 cfg.bk, cfg.stages, p.b_nk, p.c_bf16);
+                                 cfg.bk, cfg.stages, cfg.sched, p.b_nk,
+                                 p.c_bf16, chunk_multiple(L.Kc, L.gemm_dt));
         if (L.variant < 0)
             return fail(TG_E_UNSUPPORTED,
                         "no tiled kernel for dtype %d, %d x %d, waves %d x %d,"
-                        " bk %d, %d stages", L.gemm_dt, cfg.bm, cfg.bn,
-                        cfg.wm, cfg.wn, cfg.bk, cfg.stages);
+                        " bk %d, %d stages, schedule %d (ping-pong needs K a "
+                        "multiple of 16 bytes)", L.gemm_dt, cfg.bm, cfg.bn,
+                        cfg.wm, cfg.wn, cfg.bk, cfg.stages, cfg.sched);
         const TiledVariant &v = tiled_variant(L.variant);
         cfg.bk = v.bk;
         cfg.wm = v.wm;
         cfg.wn = v.wn;
         cfg.stages = v.stages;
+        cfg.sched = v.sched;
         cfg.ksplit = 1;
         L.s.tiles_m = (int32_t)((p.M + cfg.bm - 1) / cfg.bm);
         L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
@@ -443,7 +454,7 @@ void candidates(const Problem &p, const tg_in *A, const tg_in *B,
         tg_config c{};
         c.kind = TG_KIND_TILED;
         c.bm = v.bm; c.bn = v.bn; c.wm = v.wm; c.wn = v.wn;
-        c.bk = v.bk; c.stages = v.stages;
+        c.bk = v.bk; c.stages = v.stages; c.sched = v.sched;
         try_cfg(c);
     }
     // the element-wise fallback competes only where nothing else runs
@@ -486,6 +497,7 @@ void features(const Problem &p, const Launch &L, float *f) {
     f[18] = (float)(tiles / (progs * rounds));
     f[19] = (float)((double)p.M * (double)p.N /
                     (tiles * (double)c.bm * (double)c.bn));
+    f[20] = c.sched == TG_SCHED_PINGPONG ? 1.f : 0.f;
 }
 
 // Configuration when the caller gives none: the tuning cache, then the
@@ -834,8 +846,11 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
         for (auto &p : ps) work += p.M * p.N;
         cfg.bm = cfg.bn = work >= (int64_t)256 * 256 * 256 ? 256 : 128;
     }
+    bool pp_ok = true;
+    for (auto &p : ps) pp_ok = pp_ok && chunk_multiple(p.K, TG_BF16);
     int variant = find_variant(TG_BF16, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
-                               cfg.bk, cfg.stages, b_nk == 1, c_bf16 == 1);
+                               cfg.bk, cfg.stages, cfg.sched, b_nk == 1,
+                               c_bf16 == 1, pp_ok);
     if (variant < 0)
         return fail(TG_E_UNSUPPORTED, "no tiled kernel %d x %d", cfg.bm,
                     cfg.bn);

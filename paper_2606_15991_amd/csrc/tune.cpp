@@ -241,20 +241,22 @@ int32_t tile_tune_cache_size(void) {
 
 // Text format, one entry per line:
 //   M N K a_dt b_dt b_nk c_bf16 precision kind bm bn bk wm wn ksplit stages
+//   sched
 tg_status tile_tune_cache_save(const char *path) {
     if (!path) return TG_E_ARG;
     FILE *f = std::fopen(path, "w");
     if (!f) return TG_E_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    std::fprintf(f, "# tilegemm tuning cache v2\n");
+    std::fprintf(f, "# tilegemm tuning cache v3\n");
     for (const auto &kv : g_cache) {
         const Key &k = kv.first;
         const tg_config &c = kv.second;
         std::fprintf(f,
-                     "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d\n",
+                     "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d "
+                     "%d\n",
                      (long long)k.M, (long long)k.N, (long long)k.K, k.a_dt,
                      k.b_dt, k.b_nk, k.c_bf16, k.precision, c.kind, c.bm, c.bn,
-                     c.bk, c.wm, c.wn, c.ksplit, c.stages);
+                     c.bk, c.wm, c.wn, c.ksplit, c.stages, c.sched);
     }
     std::fclose(f);
     return TG_OK;
@@ -273,10 +275,11 @@ tg_status tile_tune_cache_load(const char *path) {
         Key k;
         tg_config c{};
         int n = std::sscanf(
-            line, "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d", &M,
-            &N, &K, &k.a_dt, &k.b_dt, &k.b_nk, &k.c_bf16, &k.precision,
-            &c.kind, &c.bm, &c.bn, &c.bk, &c.wm, &c.wn, &c.ksplit, &c.stages);
-        if (n != 16) {
+            line, "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d %d",
+            &M, &N, &K, &k.a_dt, &k.b_dt, &k.b_nk, &k.c_bf16, &k.precision,
+            &c.kind, &c.bm, &c.bn, &c.bk, &c.wm, &c.wn, &c.ksplit, &c.stages,
+            &c.sched);
+        if (n != 17) {
             st = TG_E_ARG;
             break;
         }

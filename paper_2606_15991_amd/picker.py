@@ -70,7 +70,7 @@ class ShapePool:
 
 def _key(cfg):
     return (cfg["kind"], cfg["bm"], cfg["bn"], cfg["bk"], cfg["wm"],
-            cfg["wn"], cfg["ksplit"], cfg["stages"])
+            cfg["wn"], cfg["ksplit"], cfg["stages"], cfg["sched"])
 
 
 def collect(shapes, pool, reps=3, log=None):

@@ -460,3 +460,141 @@ def test_decode_ragged_k(M, K, wdt):
     torch.cuda.synchronize()
     assert tuple(tg.tile_gemm.last_partition) == (16, 16)
     assert rel_err(C.cpu(), reference(x, W, True, None, s)) <= 1e-5
+
+
+# ------------------------------------------------ every tiled instantiation
+
+def _tiled_configs(A, B, C, b_trans):
+    return [c for c in tg.tile_gemm_candidates(A, B, C, b_trans=b_trans)
+            if c["kind"] == tg.TG_KIND_TILED]
+
+
+def _operands(M, N, K, b_trans, gen_a, gen_b, dtype):
+    """CPU operands from the generators and their device copies.  K = 0
+    operands are empty column slices of 16-byte rows, so that they keep a
+    leading dimension the tiled kernels accept."""
+    if K == 0:
+        A = torch.zeros((M, 0), dtype=dtype)
+        B = torch.zeros((N, 0) if b_trans else (0, N), dtype=dtype)
+        pad = 16 // A.element_size()
+        Ad = torch.zeros((M, pad), dtype=dtype, device=DEV)[:, :0]
+        Bd = (torch.zeros((N, pad), dtype=dtype, device=DEV)[:, :0]
+              if b_trans else torch.zeros((0, N), dtype=dtype, device=DEV))
+        return A, B, Ad, Bd
+    A = gen_a((M, K))
+    B = gen_b((N, K) if b_trans else (K, N))
+    return A, B, dev(A), dev(B)
+
+
+def oracle_rows(A, B, rows, b_trans, sa=None, sb=None):
+    """Oracle product restricted to the given rows of A (and of sa)."""
+    import oracle
+    return oracle.gemm(exact64(A)[rows], exact64(B), b_nk=b_trans,
+                       sa=None if sa is None else exact64(sa)[rows],
+                       sb=None if sb is None else exact64(sb))
+
+
+def _expected(A, B, b_trans, M, sa=None, sb=None, seed=0):
+    """(rows compared, oracle values there): every row of small outputs, a
+    seeded sample of 48 rows of large ones."""
+    if M * B.shape[0 if b_trans else 1] > 4096 * 4096:
+        rows = np.sort(np.random.default_rng(seed).permutation(M)[:48])
+        return rows, oracle_rows(A, B, rows, b_trans, sa, sb)
+    return None, reference(A, B, b_trans, sa, sb)
+
+
+def _pick(C, rows):
+    got = C.cpu()
+    return got if rows is None else got[torch.from_numpy(rows)]
+
+
+# (M, N, K): ragged M and N over several sub-tensors; K with a partial last
+# K tile; K = 0; and a grid of more sub-tensors than persistent programs,
+# so that programs own several each (the K-tile stream crosses sub-tensor
+# boundaries).
+EVERY_SHAPES = [(300, 264, 136), (520, 600, 328), (200, 136, 0),
+                (4352, 4352, 72)]
+
+
+@pytest.mark.parametrize("b_trans", [False, True])
+@pytest.mark.parametrize("M,N,K", EVERY_SHAPES)
+def test_every_bf16_variant_bit_exact(M, N, K, b_trans):
+    """Small-integer operands: every tiled bf16 configuration the library
+    can run for the request reproduces the oracle exactly and stores each
+    element once."""
+    A, B, Ad, Bd = _operands(
+        M, N, K, b_trans, lambda s: synth.to_bf16(synth.small_int(s, 61)),
+        lambda s: synth.to_bf16(synth.small_int(s, 62)), torch.bfloat16)
+    rows, R = _expected(A, B, b_trans, M, seed=63)
+    for out in (torch.float32, torch.bfloat16):
+        C = torch.empty((M, N), dtype=out, device=DEV)
+        cfgs = _tiled_configs(Ad, Bd, C, b_trans)
+        assert cfgs
+        want = R if out == torch.float32 else exact64(
+            torch.from_numpy(R).to(torch.bfloat16))
+        for cfg in cfgs:
+            note("every bf16", M, N, K, b_trans, out, cfg)
+            C.fill_(float("nan"))
+            wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+            tg.tile_gemm(Ad, Bd, C, cfg["bm"], cfg["bn"], b_trans=b_trans,
+                         config=cfg, write_count=wc)
+            torch.cuda.synchronize()
+            assert torch.all(wc == 1), cfg
+            assert np.array_equal(exact64(_pick(C, rows)), want), cfg
+
+
+@pytest.mark.parametrize("b_trans", [False, True])
+@pytest.mark.parametrize("M,N,K", [(300, 264, 136), (520, 600, 328),
+                                   (4352, 4352, 72)])
+def test_every_bf16_variant_normal_inputs(M, N, K, b_trans):
+    """N(0,1) bf16 operands: every tiled configuration within the binary32
+    bar."""
+    A, B, Ad, Bd = _operands(
+        M, N, K, b_trans, lambda s: synth.to_bf16(synth.normal(s, 64)),
+        lambda s: synth.to_bf16(synth.normal(s, 65)), torch.bfloat16)
+    rows, R = _expected(A, B, b_trans, M, seed=66)
+    C = torch.empty((M, N), device=DEV)
+    for cfg in _tiled_configs(Ad, Bd, C, b_trans):
+        note("every bf16 normal", M, N, K, b_trans, cfg)
+        C.fill_(float("nan"))
+        tg.tile_gemm(Ad, Bd, C, cfg["bm"], cfg["bn"], b_trans=b_trans,
+                     config=cfg)
+        torch.cuda.synchronize()
+        assert rel_err(_pick(C, rows), R) <= 1e-5, cfg
+
+
+@pytest.mark.parametrize("M,N,K", [(300, 264, 192), (4352, 4352, 128),
+                                   (200, 136, 0)])
+def test_every_fp8_variant(M, N, K):
+    """E4M3: small integers bit-exact, scaled N(0,1) within the bar, for
+    every tiled configuration."""
+    f8 = torch.float8_e4m3fn
+    ia, ib, iad, ibd = _operands(
+        M, N, K, True, lambda s: synth.small_int(s, 67).to(f8),
+        lambda s: synth.small_int(s, 68).to(f8), f8)
+    rows, Ri = _expected(ia, ib, True, M, seed=71)
+    C = torch.empty((M, N), device=DEV)
+    cfgs = _tiled_configs(iad, ibd, C, True)
+    assert cfgs
+    for cfg in cfgs:
+        note("every fp8 int", M, N, K, cfg)
+        wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+        C.fill_(float("nan"))
+        tg.tile_gemm(iad, ibd, C, cfg["bm"], cfg["bn"], b_trans=True,
+                     config=cfg, write_count=wc)
+        torch.cuda.synchronize()
+        assert torch.all(wc == 1), cfg
+        assert np.array_equal(exact64(_pick(C, rows)), Ri), cfg
+    if K == 0:
+        return
+    qa, sa = synth.quant_e4m3_rows(synth.normal((M, K), 69))
+    qb, sb = synth.quant_e4m3_rows(synth.normal((N, K), 70))
+    rows, Rq = _expected(qa, qb, True, M, sa, sb, seed=71)
+    qad, qbd, sad, sbd = dev(qa), dev(qb), dev(sa), dev(sb)
+    for cfg in cfgs:
+        note("every fp8 scaled", M, N, K, cfg)
+        C.fill_(float("nan"))
+        tg.tile_gemm(qad, qbd, C, cfg["bm"], cfg["bn"], b_trans=True,
+                     config=cfg, scale_a=sad, scale_b=sbd)
+        torch.cuda.synchronize()
+        assert rel_err(_pick(C, rows), Rq) <= FP8_BAR, cfg
