@@ -290,7 +290,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--quick", action="store_true",
                     help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
