@@ -222,7 +222,27 @@ def bench_f32_and_split(args, tg, n=8192):
     return out
 
 
+def graph_ms(calls, reps=20, warmup=3):
+    """Average ms per call of a list of launches, captured once in a HIP
+    graph and replayed (the launches are microseconds long, shorter than the
+    host's own per-call cost, so eager timing would measure the host)."""
+    s = torch.cuda.Stream()
+    for c in calls:          # eager pass: first-use set-up outside capture
+        c(None)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for c in calls:
+                c(s)
+    torch.cuda.synchronize()
+    return timed(g.replay, reps, warmup) / len(calls)
+
+
 def bench_decode(args, tg):
+    """Decode shapes: cold = the launches of one graph stream >= 1 GB of
+    distinct weight copies (more than the 256 MB Infinity Cache holds), warm
+    = the same weights every launch."""
     out = []
     for wdt in ("bf16", "fp8"):
         for (N, K) in synth.DECODE_SHAPES:
@@ -239,21 +259,21 @@ def bench_decode(args, tg):
                 copies = max(2, int(np.ceil(1.0e9 / wbytes)))
                 Ws = [W] + [W.clone() for _ in range(copies - 1)]
                 y = torch.empty((M, N), dtype=torch.bfloat16, device="cuda")
-                it = [0]
 
-                def step():
-                    tg.tile_gemm(x, Ws[it[0] % copies], y, b_trans=True,
-                                 scale_b=s)
-                    it[0] += 1
-                reps = max(copies * 4, 40)
-                ms = timed(step, reps, copies)
-                ms_warm = timed(lambda: tg.tile_gemm(x, W, y, b_trans=True,
-                                                     scale_b=s), 40, 5)
+                def call(Wi):
+                    return lambda st: tg.tile_gemm(x, Wi, y, b_trans=True,
+                                                   scale_b=s, checked=False,
+                                                   stream=st)
+                ms = graph_ms([call(Wi) for Wi in Ws], reps=10)
+                ms_warm = graph_ms([call(W)] * 20, reps=10)
+                ms_eager = timed(lambda: tg.tile_gemm(x, W, y, b_trans=True,
+                                                      scale_b=s), 40, 5)
                 nbytes = wbytes + (N * 4 if s is not None else 0) + \
                     2 * M * K + 2 * M * N
                 out.append({"w": wdt, "M": M, "N": N, "K": K,
                             "us": ms * 1e3, "gbs": nbytes / (ms * 1e-3) / 1e9,
-                            "gbs_warm": nbytes / (ms_warm * 1e-3) / 1e9})
+                            "gbs_warm": nbytes / (ms_warm * 1e-3) / 1e9,
+                            "us_eager_call": ms_eager * 1e3})
                 log("decode", out[-1])
                 del Ws, W
     return out

@@ -19,7 +19,7 @@
 namespace tg {
 namespace {
 
-constexpr int UNROLL = 4;
+constexpr int UNROLL = 8;
 
 // 16 bytes at p of which only the first n (0..16) are inside the operand;
 // the rest read as zero.  Used for the one chunk per row that straddles K.
@@ -63,41 +63,69 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
 
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     const int nsteps = (g.K + KSTEP - 1) / KSTEP;
-    // wave w takes super-steps w, w + KS, ... of UNROLL K steps each
-    for (int s0 = wave * UNROLL; s0 < nsteps; s0 += KS * UNROLL) {
-        constexpr int WES = WDT == TG_BF16 ? 2 : 1;
-        uint4 wv[UNROLL];
+    constexpr int WES = WDT == TG_BF16 ? 2 : 1;
+    constexpr int XV = WDT == TG_BF16 ? 1 : 2;   // activation chunks per step
+    const char *Xc = reinterpret_cast<const char *>(X);
+    // Wave w takes super-steps w, w + KS, ... of UNROLL K steps each: all
+    // UNROLL weight and activation chunks of a super-step are loaded before
+    // any is contracted, so every lane has UNROLL weight loads in flight
+    // (the other wavefronts of the SIMD overlap their own).  Super-steps
+    // wholly inside K load without bounds tests: rows beyond N were clamped
+    // to row N - 1 and activation rows beyond M read row 0, and both only
+    // feed outputs that are never stored.  A ragged K tail takes the checked
+    // loads.
+    uint4 wv[1][UNROLL], xv[1][UNROLL][XV];
+    auto load_fast = [&](int s0, int b) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int k = (s0 + u) * KSTEP + grp * EPL;
-            wv[u] = s0 + u < nsteps ? ld_chunk(W, k, g.K, EPL, WES)
-                                    : uint4{0, 0, 0, 0};
+            wv[b][u] = ld16(W + (int64_t)k * WES);
+#pragma unroll
+            for (int c = 0; c < XV; ++c)
+                xv[b][u][c] = ld16(Xc + (int64_t)(k + 8 * c) * 2);
         }
-        const char *Xc = reinterpret_cast<const char *>(X);
+    };
+    auto load_checked = [&](int s0, int b) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int k = (s0 + u) * KSTEP + grp * EPL;
-            const bool ok = xrow_ok && s0 + u < nsteps && k < g.K;
+            const bool live = s0 + u < nsteps;
+            wv[b][u] = live ? ld_chunk(W, k, g.K, EPL, WES) : uint4{0, 0, 0, 0};
+            const bool ok = live && k < g.K;
+#pragma unroll
+            for (int c = 0; c < XV; ++c)
+                xv[b][u][c] = ok ? ld_chunk(Xc, k + 8 * c, g.K, 8, 2)
+                                 : uint4{0, 0, 0, 0};
+        }
+    };
+    auto contract = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
             if constexpr (WDT == TG_BF16) {
-                const uint4 xv = ok ? ld_chunk(Xc, k, g.K, 8, 2)
-                                    : uint4{0, 0, 0, 0};
-                acc = mfma16_bf16(__builtin_bit_cast(i32x4, wv[u]),
-                                  __builtin_bit_cast(i32x4, xv), acc);
+                acc = mfma16_bf16(__builtin_bit_cast(i32x4, wv[b][u]),
+                                  __builtin_bit_cast(i32x4, xv[b][u][0]), acc);
             } else {
-                const uint4 x0 = ok ? ld_chunk(Xc, k, g.K, 8, 2)
-                                    : uint4{0, 0, 0, 0};
-                const uint4 x1 = ok ? ld_chunk(Xc, k + 8, g.K, 8, 2)
-                                    : uint4{0, 0, 0, 0};
-                uint2 w01 = e4m3x4_to_bf16x4(wv[u].x);
-                uint2 w23 = e4m3x4_to_bf16x4(wv[u].y);
-                uint2 w45 = e4m3x4_to_bf16x4(wv[u].z);
-                uint2 w67 = e4m3x4_to_bf16x4(wv[u].w);
+                uint2 w01 = e4m3x4_to_bf16x4(wv[b][u].x);
+                uint2 w23 = e4m3x4_to_bf16x4(wv[b][u].y);
+                uint2 w45 = e4m3x4_to_bf16x4(wv[b][u].z);
+                uint2 w67 = e4m3x4_to_bf16x4(wv[b][u].w);
                 i32x4 wa = {(int)w01.x, (int)w01.y, (int)w23.x, (int)w23.y};
                 i32x4 wb = {(int)w45.x, (int)w45.y, (int)w67.x, (int)w67.y};
-                acc = mfma16_bf16(wa, __builtin_bit_cast(i32x4, x0), acc);
-                acc = mfma16_bf16(wb, __builtin_bit_cast(i32x4, x1), acc);
+                acc = mfma16_bf16(wa, __builtin_bit_cast(i32x4, xv[b][u][0]), acc);
+                acc = mfma16_bf16(wb, __builtin_bit_cast(i32x4, xv[b][u][1]), acc);
             }
         }
+    };
+    constexpr int STRIDE = KS * UNROLL;
+    const int nfull = g.K / KSTEP;            // steps wholly inside K
+    int s0 = wave * UNROLL;
+    for (; s0 + UNROLL <= nfull; s0 += STRIDE) {
+        load_fast(s0, 0);
+        contract(0);
+    }
+    for (; s0 < nsteps; s0 += STRIDE) {       // ragged tail, bounds checked
+        load_checked(s0, 0);
+        contract(0);
     }
 
     part[wave][lane] = acc;

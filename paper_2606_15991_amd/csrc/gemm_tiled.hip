@@ -87,6 +87,12 @@ struct Cfg {
     static constexpr int B_BLK = (BK / EPC) * (BN / EPC);
     static constexpr int B_BLK_PT = (B_BLK + THREADS - 1) / THREADS;
     static constexpr int STAGE = (BM + BN) * RBY;   // bytes per LDS stage
+    // Per-row and per-column scales of an owned sub-tensor live in LDS next
+    // to the stages, one slot per sub-tensor in flight (NS + 1 slots: the
+    // loads run at most NS - 1 K tiles, hence sub-tensors, ahead).
+    static constexpr int SCALE_SLOT = (BM + BN) * 4;
+    static constexpr int NSLOT = NS + 1;
+    static constexpr int SMEM = NS * STAGE + (DIRECT ? NSLOT * SCALE_SLOT : 0);
     static constexpr int LPW = STAGE / 1024 / NW;   // 1 KiB loads per wave
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
     static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
@@ -101,6 +107,14 @@ struct Cfg {
     static_assert(!B_KMAJOR || CPR >= 4, "k-major B rows of >= 64 bytes");
     static_assert(DT != TG_FP8_E4M3 || BK >= 64, "e4m3 K tile >= 64");
     static_assert(LPW * (NS - 2) < 64, "vmcnt range");
+    // Wavefronts per SIMD when LDS limits the workgroups per CU (160 KiB):
+    // the register budget and scheduling target of the compiler.  Without
+    // it the scheduler aims at a higher occupancy than LDS allows and
+    // trades the fragment double buffer for fewer registers.
+    static constexpr int WG_PER_CU_ = 163840 / SMEM;
+    static constexpr int WPE_ = WG_PER_CU_ * NW / 4;
+    static constexpr int WPE_MAX_ = DIRECT ? 4 : 2;  // f32: register staging
+    static constexpr int WPE = WPE_ < 1 ? 1 : (WPE_ > WPE_MAX_ ? WPE_MAX_ : WPE_);
     static_assert(!PP || (DIRECT && WM == 2 && NW == 8 && NS >= 3),
                   "ping-pong: two groups of four wavefronts, >= 3 stages");
 };
@@ -235,6 +249,21 @@ __device__ __forceinline__ void dma16(const i32x4 &srd, char *dst,
             : "memory", "m0");
 }
 
+// One 4-byte-per-lane load into LDS at dst + 4 * lane (same protocol as
+// dma16).
+__device__ __forceinline__ void dma4(const i32x4 &srd, char *dst,
+                                     uint32_t voff) {
+    const uint32_t lds = __builtin_amdgcn_readfirstlane(
+        (int)static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
+            (lds_void *)dst)));
+    asm volatile(
+        "s_nop 4\n\ts_mov_b32 m0, %0\n\ts_nop 0\n\t"
+        "buffer_load_dword %1, %2, 0 offen lds"
+        :
+        : "s"(lds), "v"(voff), "s"(srd)
+        : "memory", "m0");
+}
+
 __device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
     return b <= 0 ? 0u : (b >= 0x7fffffff ? 0x7fffffffu : (uint32_t)b);
 }
@@ -300,6 +329,40 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
                 dma16<false>(srd, Bs + gi * 1024, voff);
         }
     }
+}
+
+// Scales of one owned sub-tensor into its LDS slot: scale_a[m0 .. m0+BM)
+// then scale_b[n0 .. n0+BN), 64 per instruction, instructions dealt out
+// over the wavefronts.  Entries beyond M / N load as zeros.
+template <class C>
+__device__ __forceinline__ void issue_scales(const Job &j, char *slot,
+                                             int wave, int lane) {
+    constexpr int IA = (C::BM + 63) / 64, IB = (C::BN + 63) / 64;
+    if (j.scale_a) {
+        const i32x4 srd = make_srd(j.scale_a + j.m0, sat_bytes((int64_t)(j.M - j.m0) * 4));
+#pragma unroll
+        for (int i = 0; i < IA; ++i)
+            if (i % C::NW == wave) {
+                const int r = i * 64 + lane;
+                dma4(srd, slot + i * 256, r < C::BM ? (uint32_t)(r * 4) : kOutOfRange);
+            }
+    }
+    if (j.scale_b) {
+        const i32x4 srd = make_srd(j.scale_b + j.n0, sat_bytes((int64_t)(j.N - j.n0) * 4));
+#pragma unroll
+        for (int i = 0; i < IB; ++i)
+            if ((IA + i) % C::NW == wave) {
+                const int c = i * 64 + lane;
+                dma4(srd, slot + C::BM * 4 + i * 256,
+                     c < C::BN ? (uint32_t)(c * 4) : kOutOfRange);
+            }
+    }
+}
+
+// LDS scale slot of the n-th owned sub-tensor of a program.
+template <class C>
+__device__ __forceinline__ char *scale_slot(char *smem, int n) {
+    return smem + C::NS * C::STAGE + (n % C::NSLOT) * C::SCALE_SLOT;
 }
 
 // Register-staged K tile of the f32 path.  load() issues the global reads,
@@ -518,10 +581,13 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
 // Stores go through a buffer descriptor rooted at the sub-tensor's first
 // element with 32-bit offsets; elements outside the output (rows >= M,
 // columns >= N) get an out-of-range offset, which the hardware drops.
+// `scl`: this sub-tensor's scale slot in LDS (direct-load programs), or
+// nullptr to read the scales from global memory.
 template <class C>
 __device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
                                          int lane,
-                                         f32x16 (&acc)[C::FM][C::FN]) {
+                                         f32x16 (&acc)[C::FM][C::FN],
+                                         const char *scl) {
     constexpr int OES = C::CBF16 ? 2 : 4;
     // The address arithmetic below is loop-invariant in a persistent
     // program; hidden from the optimiser so that it is formed here, per
@@ -544,14 +610,22 @@ __device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
     // Scales are loaded, and waited for, before any store is issued, and
     // inside the branch that loads them, so that no load of this epilogue
     // is outstanding (or believed outstanding) when the K loop resumes.
+    const float *lsa = reinterpret_cast<const float *>(scl);
+    const float *lsb = lsa + C::BM;
     float sb[C::FN];
 #pragma unroll
     for (int jj = 0; jj < C::FN; ++jj) sb[jj] = 1.0f;
     if (j.scale_b) {
+        if (scl) {
 #pragma unroll
-        for (int jj = 0; jj < C::FN; ++jj)
-            if (jj * 32 < cols_left) sb[jj] = j.scale_b[j.n0 + c0 + jj * 32];
-        wait_vmem();
+            for (int jj = 0; jj < C::FN; ++jj) sb[jj] = lsb[c0 + jj * 32];
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < C::FN; ++jj)
+                if (jj * 32 < cols_left)
+                    sb[jj] = j.scale_b[j.n0 + c0 + jj * 32];
+            wait_vmem();
+        }
     }
     const uint32_t lane_off = (uint32_t)((r0 * ldc + c0) * OES);
     auto store_rows = [&](int i, const float (&sa)[16]) {
@@ -583,12 +657,18 @@ __device__ __forceinline__ void epilogue(const Job &j, int wm, int wn,
 #pragma unroll
         for (int i = 0; i < C::FM; ++i) {
             float sa[16];
+            if (scl) {
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
-                sa[v] = dr < rows_left ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
+                for (int v = 0; v < 16; ++v)
+                    sa[v] = lsa[r0 + i * 32 + 8 * (v >> 2) + (v & 3)];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int dr = i * 32 + 8 * (v >> 2) + (v & 3);
+                    sa[v] = dr < rows_left ? j.scale_a[j.m0 + r0 + dr] : 1.0f;
+                }
+                wait_vmem();
             }
-            wait_vmem();
             store_rows(i, sa);
         }
     }
@@ -700,10 +780,12 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
     int t = program_slot(blockIdx.x, G);
     if (t >= total) return;
     auto stage = [&](int g) { return smem + (g % C::NS) * C::STAGE; };
+    auto slot = [&](int n) { return scale_slot<C>(smem, n); };
     Job j = prov.job(t);
-    int g = 0;
+    int g = 0, njob = 0;
     {
         const int nk = (j.K + C::BK - 1) / C::BK;
+        issue_scales<C>(j, slot(njob), wave, lane);
         for (int s = 0; s < C::NS - 1 && s < nk; ++s)
             issue_direct<C>(j, stage(g + s), s * C::BK, wave, lane);
     }
@@ -713,7 +795,10 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
         // the last K tile holds a chunk that straddles K
         const bool ragged = (j.K % C::EPC) != 0;
         zero_acc<C>(acc);
-        if (nk == 0) ring_barrier();
+        if (nk == 0) {
+            wait_vmem();      // the scales
+            ring_barrier();
+        }
         for (int kt = 0; kt < nk; ++kt) {
             const int later = nk - 1 - kt < C::NS - 2 ? nk - 1 - kt : C::NS - 2;
             if (kt == 0)
@@ -741,12 +826,14 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
         if (more) {
             nj = prov.job(t);
             const int nk2 = (nj.K + C::BK - 1) / C::BK;
+            issue_scales<C>(nj, slot(njob + 1), wave, lane);
             for (int s = 0; s < C::NS - 1 && s < nk2; ++s)
                 issue_direct<C>(nj, stage(g + s), s * C::BK, wave, lane);
         }
-        epilogue<C>(j, wm, wn, lane, acc);
+        epilogue<C>(j, wm, wn, lane, acc, slot(njob));
         if (!more) break;
         j = nj;
+        ++njob;
     }
 }
 
@@ -783,7 +870,7 @@ __device__ __forceinline__ void run_regs(const P &prov, char *smem) {
             if (nxt < nk) rt.store(smem + (nxt & 1) * C::STAGE, tid);
             __syncthreads();
         }
-        epilogue<C>(j, wm, wn, lane, acc);
+        epilogue<C>(j, wm, wn, lane, acc, nullptr);
     }
 }
 
@@ -892,26 +979,32 @@ __device__ __forceinline__ int pp_tiles(int K) {
 }
 
 // Loads of the K-tile stream in issue order: (owned sub-tensor, K tile).
+// A sub-tensor's scales are issued with its first K tile, into the LDS
+// slot of its position in the sequence of owned sub-tensors.
 template <class C, class P>
 struct LoadCursor {
     const P &prov;
     Job j;
     int t, kt, nk, total, G;
     int issued;   // tiles issued so far (stream index of the next one)
+    int njob;     // position of j among this program's sub-tensors
 
     __device__ LoadCursor(const P &p, int t0, int total_, int G_)
-        : prov(p), t(t0), kt(0), total(total_), G(G_), issued(0) {
+        : prov(p), t(t0), kt(0), total(total_), G(G_), issued(0), njob(0) {
         j = prov.job(t);
         nk = pp_tiles<C>(j.K);
     }
     __device__ __forceinline__ void issue(char *smem, int wave, int lane) {
         if (t >= total) return;
+        if (kt == 0)
+            issue_scales<C>(j, scale_slot<C>(smem, njob), wave, lane);
         issue_direct<C>(j, smem + (issued % C::NS) * C::STAGE, kt * C::BK,
                         wave, lane);
         ++issued;
         if (++kt == nk) {
             kt = 0;
             t += G;
+            ++njob;
             if (t < total) {
                 j = prov.job(t);
                 nk = pp_tiles<C>(j.K);
@@ -952,7 +1045,7 @@ __device__ __forceinline__ void run_pingpong(const P &prov, char *smem) {
     for (int s = 0; s < C::NS - 1; ++s) ld.issue(smem, wave, lane);
     Job j = prov.job(t);
     int nk = pp_tiles<C>(j.K);
-    int kt = 0, q = 0;
+    int kt = 0, q = 0, njob = 0;
     bool dirty = false;
     f32x16 acc[C::FM][C::FN];
     zero_acc<C>(acc);
@@ -975,7 +1068,8 @@ __device__ __forceinline__ void run_pingpong(const P &prov, char *smem) {
         __builtin_amdgcn_s_setprio(0);
         ++q;
         if (++kt == nk) {
-            epilogue<C>(j, wm, wn, lane, acc);
+            epilogue<C>(j, wm, wn, lane, acc, scale_slot<C>(smem, njob));
+            ++njob;
             dirty = true;
             t += G;
             if (t >= total) break;
@@ -1042,7 +1136,9 @@ struct GroupProvider {
 };
 
 template <class C>
-__global__ __launch_bounds__(C::THREADS) void gemm_tiled_kernel(GemmArgs g) {
+__global__ __launch_bounds__(C::THREADS)
+__attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_tiled_kernel(
+    GemmArgs g) {
     extern __shared__ __align__(1024) char smem[];
     SingleProvider<C> p{g};
     if constexpr (C::PP)
@@ -1054,7 +1150,8 @@ __global__ __launch_bounds__(C::THREADS) void gemm_tiled_kernel(GemmArgs g) {
 }
 
 template <class C>
-__global__ __launch_bounds__(C::THREADS) void gemm_grouped_kernel(
+__global__ __launch_bounds__(C::THREADS)
+__attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_grouped_kernel(
     const GroupProblem *__restrict__ tab, int n, int total, int G) {
     extern __shared__ __align__(1024) char smem[];
     GroupProvider<C> p{tab, n, total, G};
@@ -1085,7 +1182,7 @@ VariantEntry make_entry() {
     e.kernel = reinterpret_cast<const void *>(&gemm_tiled_kernel<C>);
     e.grouped = reinterpret_cast<const void *>(&gemm_grouped_kernel<C>);
     e.threads = C::THREADS;
-    e.smem = C::NS * C::STAGE;
+    e.smem = C::SMEM;
     return e;
 }
 
