@@ -155,7 +155,7 @@ def bench_bf16_kn(args, tg):
     A = synth.to_bf16(synth.normal((n, n), 2)).cuda()
     B = synth.to_bf16(synth.normal((n, n), 202)).cuda()
     C = torch.empty((n, n), device="cuda")
-    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256), 20, 3)
+    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256), 20, 10)
     return {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
 
 
@@ -194,7 +194,7 @@ def bench_fp8(args, tg, n=8192):
     Ad, Bd, sad, sbd = qa.cuda(), qb.cuda(), sa.cuda(), sb.cuda()
     C = torch.empty((n, n), device="cuda")
     ms = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True,
-                                    scale_a=sad, scale_b=sbd), 10, 2)
+                                    scale_a=sad, scale_b=sbd), 20, 10)
     return {"M": n, "N": n, "K": n, "ms": ms,
             "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
             "frac_fp8_peak": 2.0 * n ** 3 / (ms * 1e-3) / 1e12 /

@@ -120,15 +120,17 @@ struct Cfg {
 };
 
 // Row-major [rows][RBY bytes] operand stage: chunk c of row r sits at chunk
-// position c ^ f(r), with f(r) = (r ^ (r >> 3)) & 7 for 128-byte rows and
+// position c ^ f(r), with f(r) = (r >> 1) & 7 for 128-byte rows and
 // ((r >> 1) ^ (r >> 3)) & 3 for 64-byte rows.  Any 16 consecutive rows read
 // at one logical chunk then cover 16 distinct 16-byte bank groups of a
 // 256-byte bank window (and any 8 of them 8 groups of a 128-byte window), so
-// the 16-byte fragment reads are conflict-free.
+// the 16-byte fragment reads are conflict-free.  f is unchanged by a shift
+// of 32 rows, so the fragments of one K step, 32 rows apart, sit at one lane
+// offset plus constants.
 template <class C>
 __device__ __forceinline__ int swz_f(int row) {
     if constexpr (C::RBY == 128)
-        return (row ^ (row >> 3)) & 7;
+        return (row >> 1) & 7;
     else
         return ((row >> 1) ^ (row >> 3)) & 3;
 }
@@ -490,15 +492,20 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
     const char *As = stage;
     const char *Bs = stage + C::BM * C::RBY;
     const int r = lane & 31, half = lane >> 5;
+    // Fragment rows are wm * TM + f * 32 + r (A) and wn * TN + f * 32 + r
+    // (B): one lane offset per K step, the rest compile-time constants.
+    const int sw = swz_f<C>(r);
+    const char *Aw = As + wm * C::TM * C::RBY + r * C::RBY;
+    const char *Bw = Bs + wn * C::TN * C::RBY + r * C::RBY;
     if constexpr (C::DTYPE == TG_BF16 || C::DTYPE == TG_F32) {
         // fragments of step kk + 1 are read while the MFMAs of step kk run
         i32x4 af[2][C::FM], bfr[2][C::FN];
         auto load = [&](int kk, int s) {
-            const int c = 2 * kk + half;
+            const int co = ((2 * kk + half) ^ sw) << 4;
 #pragma unroll
             for (int f = 0; f < C::FM; ++f)
                 af[s][f] = *reinterpret_cast<const i32x4 *>(
-                    As + swz<C>(wm * C::TM + f * 32 + r, c));
+                    Aw + f * 32 * C::RBY + co);
 #pragma unroll
             for (int f = 0; f < C::FN; ++f) {
                 if constexpr (C::B_KMAJOR)
@@ -506,7 +513,7 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
                                                  lane);
                 else
                     bfr[s][f] = *reinterpret_cast<const i32x4 *>(
-                        Bs + swz<C>(wn * C::TN + f * 32 + r, c));
+                        Bw + f * 32 * C::RBY + co);
             }
         };
         constexpr int KK = C::DTYPE == TG_BF16 ? C::BK / 16 : C::BK / 8;
@@ -547,22 +554,19 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
 #pragma unroll
         for (int kk = 0; kk < C::BK / 64; ++kk) {
             const int c = 4 * kk + 2 * half;
+            const int co0 = (c ^ sw) << 4, co1 = ((c + 1) ^ sw) << 4;
             i32x8 af[C::FM], bfr[C::FN];
 #pragma unroll
             for (int f = 0; f < C::FM; ++f) {
-                const int row = wm * C::TM + f * 32 + r;
-                i32x4 lo = *reinterpret_cast<const i32x4 *>(As + swz<C>(row, c));
-                i32x4 hi =
-                    *reinterpret_cast<const i32x4 *>(As + swz<C>(row, c + 1));
+                i32x4 lo = *reinterpret_cast<const i32x4 *>(Aw + f * 32 * C::RBY + co0);
+                i32x4 hi = *reinterpret_cast<const i32x4 *>(Aw + f * 32 * C::RBY + co1);
                 af[f] = i32x8{lo[0], lo[1], lo[2], lo[3],
                               hi[0], hi[1], hi[2], hi[3]};
             }
 #pragma unroll
             for (int f = 0; f < C::FN; ++f) {
-                const int row = wn * C::TN + f * 32 + r;
-                i32x4 lo = *reinterpret_cast<const i32x4 *>(Bs + swz<C>(row, c));
-                i32x4 hi =
-                    *reinterpret_cast<const i32x4 *>(Bs + swz<C>(row, c + 1));
+                i32x4 lo = *reinterpret_cast<const i32x4 *>(Bw + f * 32 * C::RBY + co0);
+                i32x4 hi = *reinterpret_cast<const i32x4 *>(Bw + f * 32 * C::RBY + co1);
                 bfr[f] = i32x8{lo[0], lo[1], lo[2], lo[3],
                                hi[0], hi[1], hi[2], hi[3]};
             }
