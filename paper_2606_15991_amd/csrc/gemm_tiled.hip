@@ -300,10 +300,15 @@ __device__ __forceinline__ void issue_operand(const char *mat, int64_t ld,
     }
 }
 
+// parts: bit 0 = the A tile, bit 1 = the B tile.
 template <class C>
 __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
-                                             int k0, int wave, int lane) {
-    issue_operand<C, C::BM>(j.a, j.lda, j.m0, j.M, k0, j.K, stage, wave, lane);
+                                             int k0, int wave, int lane,
+                                             int parts = 3) {
+    if (parts & 1)
+        issue_operand<C, C::BM>(j.a, j.lda, j.m0, j.M, k0, j.K, stage, wave,
+                                lane);
+    if (!(parts & 2)) return;
     char *Bs = stage + C::BM * C::RBY;
     if constexpr (!C::B_KMAJOR) {
         issue_operand<C, C::BN>(j.b, j.ldb, j.n0, j.N, k0, j.K, Bs, wave,
@@ -485,10 +490,14 @@ __device__ __forceinline__ i32x4 read_b_kmajor(const char *Bs, int kk,
     return out;
 }
 
-template <class C>
+// hook(kk, KK) runs once per K step kk (after the step's fragment reads are
+// issued for bf16 and f32, before them for e4m3); the direct-load programs
+// issue the next K tile's loads from it.
+template <class C, class Hook>
 __device__ __forceinline__ void compute_stage(const char *stage, int wm,
                                               int wn, int lane,
-                                              f32x16 (&acc)[C::FM][C::FN]) {
+                                              f32x16 (&acc)[C::FM][C::FN],
+                                              Hook hook) {
     const char *As = stage;
     const char *Bs = stage + C::BM * C::RBY;
     const int r = lane & 31, half = lane >> 5;
@@ -522,6 +531,7 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
         for (int kk = 0; kk < KK; ++kk) {
             const int s = kk & 1;
             if (kk + 1 < KK) load(kk + 1, s ^ 1);
+            hook(kk, KK);
             if constexpr (C::DTYPE == TG_BF16 && C::FM * C::FN >= 8) {
                 // interleave the next step's LDS reads with this step's
                 // MFMAs: one read after each of the first MFMAs
@@ -553,6 +563,7 @@ __device__ __forceinline__ void compute_stage(const char *stage, int wm,
     } else {
 #pragma unroll
         for (int kk = 0; kk < C::BK / 64; ++kk) {
+            hook(kk, C::BK / 64);   // before this step's fragments are live
             const int c = 4 * kk + 2 * half;
             const int co0 = (c ^ sw) << 4, co1 = ((c + 1) ^ sw) << 4;
             i32x8 af[C::FM], bfr[C::FN];
@@ -815,11 +826,21 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
                 __syncthreads();
             }
             // the stage of tile kt - 1 is free: every wavefront passed the
-            // barrier above after contracting it
-            if (kt + C::NS - 1 < nk)
-                issue_direct<C>(j, stage(g + kt + C::NS - 1),
-                                (kt + C::NS - 1) * C::BK, wave, lane);
-            compute_stage<C>(stage(g + kt), wm, wn, lane, acc);
+            // barrier above after contracting it.  The loads of tile
+            // kt + NS - 1 are issued inside the contraction, the A tile
+            // after the first K step's fragment reads and the B tile one
+            // step later, so the MFMA pipe is fed while they issue.
+            const bool nxt = kt + C::NS - 1 < nk;
+            compute_stage<C>(stage(g + kt), wm, wn, lane, acc,
+                             [&](int kk, int KK) {
+                if (!nxt) return;
+                const int parts = (kk == 0 ? 1 : 0) |
+                                  (kk == (KK > 1 ? 1 : 0) ? 2 : 0);
+                if (parts)
+                    issue_direct<C>(j, stage(g + kt + C::NS - 1),
+                                    (kt + C::NS - 1) * C::BK, wave, lane,
+                                    parts);
+            });
         }
         g += nk;
         // first tiles of the next owned sub-tensor, then store this one; the
@@ -870,7 +891,8 @@ __device__ __forceinline__ void run_regs(const P &prov, char *smem) {
                 rt.template load<false>(j, nxt * C::BK, tid);
             else if (nxt < nk)
                 rt.template load<true>(j, nxt * C::BK, tid);
-            compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc);
+            compute_stage<C>(smem + (kt & 1) * C::STAGE, wm, wn, lane, acc,
+                             [](int, int) {});
             if (nxt < nk) rt.store(smem + (nxt & 1) * C::STAGE, tid);
             __syncthreads();
         }
