@@ -291,6 +291,24 @@ tg_status tile_autotune(const tg_in *A, const tg_in *B, tg_out *C,
                         tg_tune_result *results, int32_t max_results,
                         int32_t *n_results, tg_config *best, tg_stream stream);
 
+/*
+ * tile_autotune_grouped -- the autotuner for one grouped launch: every tiled
+ * configuration the launch can run (bf16, the problems' B layout and C
+ * type) is prepared into `workspace`, launched once (warm-up) and then
+ * `reps` times on `stream`, timed with HIP events; the workspace is left
+ * prepared with the fastest, which *best receives (host, may be NULL), and
+ * C[i].bm / C[i].bn hold its partition.  Arguments as for
+ * tile_gemm_grouped_prepare, whose opts->config it ignores.  Outputs are
+ * written (any candidate's results).  Synchronises the stream: not
+ * capturable.
+ */
+tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
+                                tg_out *C, const tg_opts *opts,
+                                void *workspace, size_t workspace_bytes,
+                                int32_t reps, tg_tune_result *results,
+                                int32_t max_results, int32_t *n_results,
+                                tg_config *best, tg_stream stream);
+
 /* Tuning cache: clear, count, save to / merge from a text file (host). */
 tg_status tile_tune_cache_clear(void);
 int32_t tile_tune_cache_size(void);

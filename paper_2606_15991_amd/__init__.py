@@ -130,6 +130,11 @@ def _load():
     lib.tile_autotune.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                                   i32, P(tg_tune_result), i32, P(i32),
                                   P(tg_config), vp]
+    lib.tile_autotune_grouped.argtypes = [i32, P(tg_in), P(tg_in), P(tg_out),
+                                          P(tg_opts), vp, ctypes.c_size_t,
+                                          i32, P(tg_tune_result), i32, P(i32),
+                                          P(tg_config), vp]
+    lib.tile_autotune_grouped.restype = i32
     lib.tile_tune_cache_clear.argtypes = []
     lib.tile_tune_cache_size.argtypes = []
     lib.tile_tune_cache_size.restype = i32
@@ -351,6 +356,32 @@ def tile_gemm_grouped_prepare(As, Bs, Cs, *, b_trans=False, config=None,
         workspace.numel() * workspace.element_size(), _stream(stream)))
     return GroupedLaunch(As, Bs, Cs, workspace,
                          [(oc[i].bm, oc[i].bn) for i in range(n)])
+
+
+def tile_autotune_grouped(As, Bs, Cs, *, b_trans=False, reps=3,
+                          workspace=None, stream=None):
+    """Time every tiled configuration of one grouped launch; returns
+    (GroupedLaunch prepared with the fastest, best config dict,
+    [(cfg, ms, status)])."""
+    n = len(As)
+    ia = (tg_in * n)(*[make_in(a) for a in As])
+    ib = (tg_in * n)(*[make_in(b, b_trans) for b in Bs])
+    oc = (tg_out * n)(*[make_out(c) for c in Cs])
+    need = tile_gemm_grouped_workspace_size(n)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=Cs[0].device)
+    res = (tg_tune_result * 64)()
+    nres = ctypes.c_int32(0)
+    best = tg_config()
+    _raise(lib.tile_autotune_grouped(
+        n, ia, ib, oc, make_opts(), workspace.data_ptr(),
+        workspace.numel() * workspace.element_size(), int(reps), res, 64,
+        ctypes.byref(nres), ctypes.byref(best), _stream(stream)))
+    rows = [(res[i].cfg.as_dict(), float(res[i].ms), int(res[i].status))
+            for i in range(nres.value)]
+    launch = GroupedLaunch(As, Bs, Cs, workspace,
+                           [(oc[i].bm, oc[i].bn) for i in range(n)])
+    return launch, best.as_dict(), rows
 
 
 def tile_gemm_grouped(launch: GroupedLaunch, stream=None):

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "host_internal.hpp"
+#include "tg_internal.hpp"
 
 namespace tg {
 namespace host {
@@ -225,6 +226,80 @@ tg_status tile_autotune(const tg_in *A, const tg_in *B, tg_out *C,
     if (bi < 0) return TG_E_UNSUPPORTED;
     if (best) *best = cands[bi];
     cache_put(key_from(A, B, C, opts), cands[bi]);
+    return TG_OK;
+}
+
+tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
+                                tg_out *C, const tg_opts *opts,
+                                void *workspace, size_t workspace_bytes,
+                                int32_t reps, tg_tune_result *results,
+                                int32_t max_results, int32_t *n_results,
+                                tg_config *best, tg_stream stream) {
+    if (n <= 0 || !A || !B || !C || !workspace || reps <= 0) return TG_E_ARG;
+    const int b_nk = B[0].trans, c_bf16 = C[0].dtype == TG_BF16;
+    std::vector<tg_config> cands;
+    for (int i = 0; i < tiled_variant_count(); ++i) {
+        const TiledVariant &v = tiled_variant(i);
+        if (v.dtype != TG_BF16 || v.b_nk != b_nk || v.c_bf16 != c_bf16)
+            continue;
+        tg_config c{};
+        c.kind = TG_KIND_TILED;
+        c.bm = v.bm; c.bn = v.bn; c.bk = v.bk; c.wm = v.wm; c.wn = v.wn;
+        c.stages = v.stages; c.sched = v.sched; c.ksplit = 1;
+        cands.push_back(c);
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return TG_E_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return TG_E_HIP;
+    }
+    tg_opts o{};
+    if (opts) o = *opts;
+    o.write_count = nullptr;
+    int32_t bi = -1, nr = 0;
+    float best_ms = 0.f;
+    tg_status ret = TG_OK;
+    for (size_t i = 0; i < cands.size(); ++i) {
+        o.config = &cands[i];
+        tg_status st = tile_gemm_grouped_prepare(n, A, B, C, &o, workspace,
+                                                 workspace_bytes, stream);
+        if (st == TG_OK) st = tile_gemm_grouped(workspace, stream);
+        float ms = -1.f;
+        if (st == TG_OK) {
+            (void)hipEventRecord(e0, hs);
+            for (int32_t r = 0; r < reps && st == TG_OK; ++r)
+                st = tile_gemm_grouped(workspace, stream);
+            (void)hipEventRecord(e1, hs);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                ret = TG_E_HIP;
+                break;
+            }
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= (float)reps;
+        }
+        if (results && nr < max_results) {
+            results[nr].cfg = cands[i];
+            results[nr].ms = st == TG_OK ? ms : -1.f;
+            results[nr].status = st;
+            ++nr;
+        }
+        if (st == TG_OK && (bi < 0 || ms < best_ms)) {
+            bi = (int32_t)i;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_results) *n_results = nr;
+    if (ret != TG_OK) return ret;
+    if (bi < 0) return TG_E_UNSUPPORTED;
+    o.config = &cands[bi];
+    tg_status st = tile_gemm_grouped_prepare(n, A, B, C, &o, workspace,
+                                             workspace_bytes, stream);
+    if (st != TG_OK) return st;
+    if (best) *best = cands[bi];
     return TG_OK;
 }
 

@@ -390,6 +390,39 @@ def test_grouped_matches_oracle_and_single_launches():
             assert torch.equal(c, e), rep
 
 
+def test_grouped_autotuner_picks_fastest_and_matches_oracle():
+    """tile_autotune_grouped times every tiled configuration of the launch
+    (B stored N x K, bf16 output here), leaves the workspace prepared with
+    the fastest, and that launch reproduces the oracle and the single
+    launches of the same configuration."""
+    shapes = [(1, 256, 128), (300, 384, 512), (520, 640, 256), (64, 512, 640),
+              (1000, 256, 384)]
+    note("grouped autotune", shapes)
+    As = [dev(synth.to_bf16(synth.normal((m, k), 180 + i)))
+          for i, (m, n, k) in enumerate(shapes)]
+    Bs = [dev(synth.to_bf16(synth.normal((n, k), 190 + i)))
+          for i, (m, n, k) in enumerate(shapes)]
+    Cs = [torch.full((m, n), float("nan"), dtype=torch.bfloat16, device=DEV)
+          for m, n, k in shapes]
+    launch, best, rows = tg.tile_autotune_grouped(As, Bs, Cs, b_trans=True,
+                                                  reps=2)
+    assert len(rows) >= 4
+    assert all(st == 0 and ms > 0 for _, ms, st in rows)
+    assert best == min(rows, key=lambda r: r[1])[0]
+    for c in Cs:
+        c.fill_(float("nan"))
+    tg.tile_gemm_grouped(launch)
+    torch.cuda.synchronize()
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        R = reference(A.cpu(), B.cpu(), True)
+        assert rel_err(C.cpu(), R) <= 4e-3, i
+        single = torch.empty_like(C)
+        tg.tile_gemm(A, B, single, best["bm"], best["bn"], b_trans=True,
+                     config=best)
+        torch.cuda.synchronize()
+        assert torch.equal(single, C), i
+
+
 # ------------------------------------------------------------- ragged K
 
 def dev_padded(t, mult=16):
