@@ -126,9 +126,12 @@ typedef enum tg_kind {
 typedef enum tg_sched {
     TG_SCHED_ANY = 0,
     TG_SCHED_LOCKSTEP = 1, /* all wavefronts load, then all contract         */
-    TG_SCHED_PINGPONG = 2  /* two wavefront groups alternate between loading
+    TG_SCHED_PINGPONG = 2, /* two wavefront groups alternate between loading
                               and contracting, one phase apart; needs K a
                               multiple of 16 bytes of the operand type      */
+    TG_SCHED_CROSS = 3     /* lock-step with the hand-over barrier of the
+                              next K tile placed before the last K step of
+                              the current one (bf16)                        */
 } tg_sched;
 
 typedef struct tg_config {
@@ -320,16 +323,17 @@ tg_status tile_tune_cache_load(const char *path);
  * pair, in this order: log2 M, N, K; flags for e4m3 operands, f32 operands,
  * B stored N x K and a bf16 output; the kernel kind (three one-hot flags:
  * tiled, skinny, simple); log2 bm, bn, wavefronts per program, LDS stages
- * and ksplit; a ping-pong schedule flag; log2 of the sub-tensor count, of the program count and of the
- * sub-tensors per program; the fraction of the last round of sub-tensors
- * that has work; the useful fraction of the padded output area.
+ * and ksplit; log2 of the sub-tensor count, of the program count and of
+ * the sub-tensors per program; the fraction of the last round of
+ * sub-tensors that has work; the useful fraction of the padded output
+ * area; flags for the ping-pong and the cross-tile schedule.
  * tile_picker_set installs a cost model (host copy of the parameters in the
  * layout of tile_mlp_*, with per-feature mean and standard deviation used
  * to normalise the features); params == NULL removes it.
  * tile_picker_mode(mode) sets bit 1 = use the tuning cache, bit 2 = use the
  * cost model (mode < 0 only queries) and returns the previous mode.
  */
-#define TG_PICKER_FEATURES 21
+#define TG_PICKER_FEATURES 22
 tg_status tile_picker_features(const tg_in *A, const tg_in *B,
                                const tg_out *C, const tg_config *cfg,
                                float *feat);

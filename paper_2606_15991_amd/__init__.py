@@ -32,7 +32,7 @@ TG_PREC_NATIVE, TG_PREC_BF16X3, TG_PREC_BF16X6 = 0, 1, 2
 # tg_kind
 TG_KIND_AUTO, TG_KIND_TILED, TG_KIND_SKINNY, TG_KIND_SIMPLE = 0, 1, 2, 3
 # tg_sched
-TG_SCHED_ANY, TG_SCHED_LOCKSTEP, TG_SCHED_PINGPONG = 0, 1, 2
+TG_SCHED_ANY, TG_SCHED_LOCKSTEP, TG_SCHED_PINGPONG, TG_SCHED_CROSS = 0, 1, 2, 3
 TG_ERROR_NORM_DOUBLES = 514
 
 PRECISIONS = {"native": TG_PREC_NATIVE, "bf16x3": TG_PREC_BF16X3,
@@ -79,7 +79,7 @@ class tg_tune_result(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
-TG_PICKER_FEATURES = 21
+TG_PICKER_FEATURES = 22
 
 
 class TileGemmError(RuntimeError):

@@ -60,7 +60,7 @@ struct DtypeTraits<TG_FP8_E4M3> {
 };
 
 template <int DT, int BM_, int BN_, int WM_, int WN_, bool BNK_, bool CBF16_,
-          int RBY_ = 128, int NS_ = 2, bool PP_ = false>
+          int RBY_ = 128, int NS_ = 2, int SCH_ = TG_SCHED_LOCKSTEP>
 struct Cfg {
     static constexpr int DTYPE = DT;
     static constexpr int BM = BM_, BN = BN_, WM = WM_, WN = WN_;
@@ -69,7 +69,9 @@ struct Cfg {
     static constexpr int EPC = 16 / ES;         // elements per 16-byte chunk
     static constexpr int RBY = RBY_;            // bytes of K per operand row
     static constexpr int NS = NS_;              // LDS stages in the ring
-    static constexpr bool PP = PP_;             // ping-pong wave schedule
+    static constexpr int SCHED = SCH_;          // wavefront schedule
+    static constexpr bool PP = SCH_ == TG_SCHED_PINGPONG;
+    static constexpr bool XT = SCH_ == TG_SCHED_CROSS;
     static constexpr int BK = RBY / ES;         // K elements per K tile
     static constexpr int CPRW = RBY / 16;       // 16-byte chunks per row
     static constexpr int RPK = 1024 / RBY;      // rows per 1 KiB block
@@ -117,6 +119,8 @@ struct Cfg {
     static constexpr int WPE = WPE_ < 1 ? 1 : (WPE_ > WPE_MAX_ ? WPE_MAX_ : WPE_);
     static_assert(!PP || (DIRECT && WM == 2 && NW == 8 && NS >= 3),
                   "ping-pong: two groups of four wavefronts, >= 3 stages");
+    static_assert(!XT || (DIRECT && DT == TG_BF16 && (BK / 16) % 2 == 0),
+                  "cross-tile schedule: bf16, even number of K steps");
 };
 
 // Row-major [rows][RBY bytes] operand stage: chunk c of row r sits at chunk
@@ -862,6 +866,151 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
     }
 }
 
+// bf16 fragments of K step kk of a stage: FM A fragments (rows
+// wm * TM + f * 32 + lane % 32) and FN B fragments, eight k each.
+template <class C>
+__device__ __forceinline__ void read_frags(const char *stage, int wm, int wn,
+                                           int lane, int kk,
+                                           i32x4 (&af)[C::FM],
+                                           i32x4 (&bf)[C::FN]) {
+    const char *As = stage;
+    const char *Bs = stage + C::BM * C::RBY;
+    const int r = lane & 31, half = lane >> 5;
+    const int co = ((2 * kk + half) ^ swz_f<C>(r)) << 4;
+    const char *Aw = As + wm * C::TM * C::RBY + r * C::RBY + co;
+#pragma unroll
+    for (int f = 0; f < C::FM; ++f)
+        af[f] = *reinterpret_cast<const i32x4 *>(Aw + f * 32 * C::RBY);
+#pragma unroll
+    for (int f = 0; f < C::FN; ++f) {
+        if constexpr (C::B_KMAJOR)
+            bf[f] = read_b_kmajor<C>(Bs, kk, wn * C::TN + f * 32, lane);
+        else
+            bf[f] = *reinterpret_cast<const i32x4 *>(
+                Bs + (wn * C::TN + f * 32 + r) * C::RBY + co);
+    }
+}
+
+// The MFMAs of one K step, with the fragment reads issued just before
+// them interleaved one by one (NR of them).
+template <class C, int NR>
+__device__ __forceinline__ void mfma_step(const i32x4 (&af)[C::FM],
+                                          const i32x4 (&bf)[C::FN],
+                                          f32x16 (&acc)[C::FM][C::FN]) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < C::FN; ++jj)
+            acc[i][jj] = mfma_bf16(af[i], bf[jj], acc[i][jj]);
+}
+
+// Cross-tile schedule (bf16).  The barrier that hands over K tile kt + 1
+// sits before the last K step of tile kt instead of after it: every
+// wavefront has read all of tile kt's fragments by then, so the stage of
+// tile kt is free for the loads of tile kt + NS, and the first fragments
+// of tile kt + 1 are read while the last MFMAs of tile kt run.  The wait
+// for the barrier and the LDS latency of the next tile's first reads are
+// thereby covered by MFMA work.  Same ring and load accounting as the
+// lock-step loop: tile g in stage g % NS, every wavefront issues LPW loads
+// per tile in tile order.
+template <class C, class P>
+__device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
+    constexpr int KK = C::BK / 16;                 // K steps per tile (even)
+    constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    int t = program_slot(blockIdx.x, G);
+    if (t >= total) return;
+    auto stage = [&](int g) { return smem + (g % C::NS) * C::STAGE; };
+    Job j = prov.job(t);
+    int g = 0;
+    {
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        for (int s = 0; s < C::NS - 1 && s < nk; ++s)
+            issue_direct<C>(j, stage(g + s), s * C::BK, wave, lane);
+    }
+    f32x16 acc[C::FM][C::FN];
+    i32x4 fa[2][C::FM], fb[2][C::FN];
+    while (true) {
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        const bool ragged = (j.K % C::EPC) != 0;
+        zero_acc<C>(acc);
+        wait_vmem();          // also covers the previous sub-tensor's stores
+        ring_barrier();
+        if (nk > 0) {
+            if (ragged && nk == 1) {
+                fill_k_tail<C>(j, stage(g), 0, tid);
+                __syncthreads();
+            }
+            // the stage of the previous sub-tensor's last tile is free
+            if (C::NS - 1 < nk)
+                issue_direct<C>(j, stage(g + C::NS - 1),
+                                (C::NS - 1) * C::BK, wave, lane);
+            read_frags<C>(stage(g), wm, wn, lane, 0, fa[0], fb[0]);
+        }
+        int pend_b = -1;      // tile whose B loads are still to be issued
+        for (int kt = 0; kt < nk; ++kt) {
+            char *st = stage(g + kt);
+#pragma unroll
+            for (int kk = 0; kk < KK - 1; ++kk) {
+                const int s = kk & 1;
+                read_frags<C>(st, wm, wn, lane, kk + 1, fa[s ^ 1], fb[s ^ 1]);
+                mfma_step<C, NR>(fa[s], fb[s], acc);
+                if (kk == 0 && pend_b >= 0) {
+                    issue_direct<C>(j, stage(g + pend_b), pend_b * C::BK,
+                                    wave, lane, 2);
+                    pend_b = -1;
+                }
+            }
+            // tile kt + 1 has landed for every wavefront and nobody reads
+            // tile kt any more.  After the last tile the barrier and the
+            // reads of the (unused) next stage still run, keeping the loop
+            // free of a second copy of the MFMAs.
+            const int later = nk - 2 - kt < C::NS - 2 ? nk - 2 - kt
+                                                      : C::NS - 2;
+            // (pinned: the scheduler would otherwise hoist the barrier
+            // above the MFMAs of the previous steps)
+            __builtin_amdgcn_sched_barrier(0);
+            wait_tile<C>(later);
+            ring_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if (ragged && kt + 1 == nk - 1) {
+                fill_k_tail<C>(j, stage(g + kt + 1), (kt + 1) * C::BK, tid);
+                __syncthreads();
+            }
+            read_frags<C>(stage(g + kt + 1), wm, wn, lane, 0, fa[0], fb[0]);
+            mfma_step<C, NR>(fa[1], fb[1], acc);
+            if (kt + C::NS < nk) {
+                issue_direct<C>(j, st, (kt + C::NS) * C::BK, wave, lane, 1);
+                pend_b = kt + C::NS;
+            }
+        }
+        g += nk;
+        // first tiles of the next owned sub-tensor into every stage but the
+        // one of the last tile contracted, then store this one
+        t += G;
+        const bool more = t < total;
+        Job nj;
+        if (more) {
+            nj = prov.job(t);
+            const int nk2 = (nj.K + C::BK - 1) / C::BK;
+            for (int s = 0; s < C::NS - 1 && s < nk2; ++s)
+                issue_direct<C>(nj, stage(g + s), s * C::BK, wave, lane);
+        }
+        epilogue<C>(j, wm, wn, lane, acc, nullptr);
+        if (!more) break;
+        j = nj;
+    }
+}
+
 // Register-staged programs (f32).
 template <class C, class P>
 __device__ __forceinline__ void run_regs(const P &prov, char *smem) {
@@ -1169,6 +1318,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_tiled_kernel(
     SingleProvider<C> p{g};
     if constexpr (C::PP)
         run_pingpong<C>(p, smem);
+    else if constexpr (C::XT)
+        run_direct_xt<C>(p, smem);
     else if constexpr (C::DIRECT)
         run_direct<C>(p, smem);
     else
@@ -1183,6 +1334,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_grouped_kernel(
     GroupProvider<C> p{tab, n, total, G};
     if constexpr (C::PP)
         run_pingpong<C>(p, smem);
+    else if constexpr (C::XT)
+        run_direct_xt<C>(p, smem);
     else if constexpr (C::DIRECT)
         run_direct<C>(p, smem);
     else
@@ -1202,7 +1355,7 @@ VariantEntry make_entry() {
     VariantEntry e;
     e.v.dtype = C::DTYPE;
     e.v.bm = C::BM; e.v.bn = C::BN; e.v.bk = C::BK; e.v.stages = C::NS;
-    e.v.sched = C::PP ? TG_SCHED_PINGPONG : TG_SCHED_LOCKSTEP;
+    e.v.sched = C::SCHED;
     e.v.wm = C::WM; e.v.wn = C::WN;
     e.v.b_nk = C::BNK; e.v.c_bf16 = C::CBF16;
     e.kernel = reinterpret_cast<const void *>(&gemm_tiled_kernel<C>);
@@ -1223,22 +1376,33 @@ VariantEntry make_entry() {
         make_entry<Cfg<DT, BM, BN, WM, WN, true, true, RBY, NS>>()
 
 #define TG_VARIANTS_PP(DT, BM, BN, RBY, NS)                                   \
-    make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, true>>(),         \
-        make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, true>>(),      \
-        make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, true>>(),      \
-        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, true>>()
+    make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, TG_SCHED_PINGPONG>>(),         \
+        make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, TG_SCHED_PINGPONG>>(),      \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, TG_SCHED_PINGPONG>>(),      \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, TG_SCHED_PINGPONG>>()
+
+#define TG_VARIANTS_XT_NK(DT, BM, BN, RBY, NS)                                \
+    make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, TG_SCHED_CROSS>>(), \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, TG_SCHED_CROSS>>()
+
+#define TG_VARIANTS_XT_KN(DT, BM, BN, RBY, NS)                                \
+    make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, TG_SCHED_CROSS>>(), \
+        make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, TG_SCHED_CROSS>>()
 
 #define TG_VARIANTS_PP_NK(DT, BM, BN, RBY, NS)                                \
-    make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, true>>(),          \
-        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, true>>()
+    make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, TG_SCHED_PINGPONG>>(),          \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, TG_SCHED_PINGPONG>>()
 
 // Table order is preference order: the first variant matching a request's
 // dtype, partition, layout and output type is the default.
 const VariantEntry *table(int *count) {
     static const VariantEntry entries[] = {
+        TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 128, 2),
         TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 128, 2),
+        TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 128, 2),
         TG_VARIANTS_PP(TG_BF16, 256, 256, 64, 4),
-        TG_VARIANTS_FOR(TG_BF16, 256, 256, 2, 4, 64, 4),
+        TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 4),
+        TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2, 128, 2),

@@ -498,6 +498,7 @@ void features(const Problem &p, const Launch &L, float *f) {
     f[19] = (float)((double)p.M * (double)p.N /
                     (tiles * (double)c.bm * (double)c.bn));
     f[20] = c.sched == TG_SCHED_PINGPONG ? 1.f : 0.f;
+    f[21] = c.sched == TG_SCHED_CROSS ? 1.f : 0.f;
 }
 
 // Configuration when the caller gives none: the tuning cache, then the

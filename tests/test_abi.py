@@ -274,7 +274,8 @@ def test_picker_features_describe_the_configuration():
                 np.log2(max(cfg["ksplit"], 1)), np.log2(tiles),
                 np.log2(n_prog), np.log2(rounds),
                 tiles / (n_prog * rounds), 1.0,
-                1.0 if cfg["sched"] == tg.TG_SCHED_PINGPONG else 0.0]
+                1.0 if cfg["sched"] == tg.TG_SCHED_PINGPONG else 0.0,
+                1.0 if cfg["sched"] == tg.TG_SCHED_CROSS else 0.0]
         assert np.allclose(f, want, rtol=0, atol=1e-6), (cfg, f)
         seen.add(tuple(f))
     # every candidate is distinguishable by its features
