@@ -94,11 +94,14 @@ struct Cfg {
     // loads run at most NS - 1 K tiles, hence sub-tensors, ahead).
     static constexpr int SCALE_SLOT = (BM + BN) * 4;
     static constexpr int NSLOT = NS + 1;
-    static constexpr int SMEM = NS * STAGE + (DIRECT ? NSLOT * SCALE_SLOT : 0);
+    static constexpr int SMEM =
+        NS * STAGE + (DIRECT && SCH_ != TG_SCHED_CROSS ? NSLOT * SCALE_SLOT : 0);
     static constexpr int LPW = STAGE / 1024 / NW;   // 1 KiB loads per wave
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
     static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
-    static_assert(NS == 2 || NS == 4, "ring of 2 or 4 stages");
+    static_assert(NS == 2 || NS == 4 || (NS == 5 && SCH_ == TG_SCHED_CROSS &&
+                                         RBY == 64),
+                  "ring of 2 or 4 stages, or 5 of 64-byte rows");
     static_assert(DIRECT || (RBY == 128 && NS == 2), "f32 register path");
     static_assert((BM / RPK) % NW == 0, "A 1 KiB blocks per wave");
     static_assert(B_KMAJOR ? (BK * RB / 1024) % NW == 0
@@ -1011,6 +1014,111 @@ __device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
     }
 }
 
+// Cross-tile schedule over a ring of five 32-deep slots (bf16, 64-byte K
+// rows; five slots fill the 160 KiB of LDS).  The hand-over barrier comes
+// every second slot (a 64-deep unit, four K steps), before the unit's last
+// K step as in run_direct_xt.  At a hand-over the two slots of the next
+// unit have landed and the slot after them may still be in flight, so half
+// of the loads of every unit have two unit periods to land and only the
+// other half has one.  Slot q of a sub-tensor (running index g + q) lives
+// at position (g + q) % 5; a sub-tensor with an odd number of slots gets
+// one more, past K, which loads as zeros.  Per wavefront, slot q is issued
+// as one group of LPW loads: slots 0 .. 2 before the sub-tensor's first
+// barrier (with the previous sub-tensor's store), slot 2u + 3 after the
+// last K step of unit u - 1 and slot 2u + 4 after the first K step of unit
+// u, so that the hand-over of unit u waits for all but slot 2u + 4.
+template <class C, class P>
+__device__ __forceinline__ void run_direct_x5(const P &prov, char *smem) {
+    static_assert(C::NS == 5 && C::BK == 32, "five slots of 32 K");
+    constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    int t = program_slot(blockIdx.x, G);
+    if (t >= total) return;
+    auto slot = [&](int q) { return smem + (q % 5) * C::STAGE; };
+    auto nslots = [&](const Job &jb) {
+        return (((jb.K + C::BK - 1) / C::BK) + 1) & ~1;
+    };
+    Job j = prov.job(t);
+    int g = 0;
+    {
+        const int nq = nslots(j);
+        for (int q = 0; q < 3 && q < nq; ++q)
+            issue_direct<C>(j, slot(g + q), q * C::BK, wave, lane);
+    }
+    f32x16 acc[C::FM][C::FN];
+    i32x4 fa[2][C::FM], fb[2][C::FN];
+    while (true) {
+        const int nq = nslots(j), nu = nq / 2;
+        const bool ragged = (j.K % C::EPC) != 0;
+        const int qtail = (j.K + C::BK - 1) / C::BK - 1;  // straddling chunk
+        zero_acc<C>(acc);
+        wait_vmem();          // also covers the previous sub-tensor's stores
+        ring_barrier();
+        int pend = -1;        // slot to issue after the next first K step
+        if (nu > 0) {
+            if (ragged && qtail <= 1) {
+                fill_k_tail<C>(j, slot(g + qtail), qtail * C::BK, tid);
+                __syncthreads();
+            }
+            if (3 < nq) issue_direct<C>(j, slot(g + 3), 3 * C::BK, wave, lane);
+            if (4 < nq) pend = 4;
+            read_frags<C>(slot(g), wm, wn, lane, 0, fa[0], fb[0]);
+        }
+        for (int u = 0; u < nu; ++u) {
+            char *sa = slot(g + 2 * u), *sb = slot(g + 2 * u + 1);
+            read_frags<C>(sa, wm, wn, lane, 1, fa[1], fb[1]);
+            mfma_step<C, NR>(fa[0], fb[0], acc);
+            if (pend >= 0) {
+                issue_direct<C>(j, slot(g + pend), pend * C::BK, wave, lane);
+                pend = -1;
+            }
+            read_frags<C>(sb, wm, wn, lane, 0, fa[0], fb[0]);
+            mfma_step<C, NR>(fa[1], fb[1], acc);
+            read_frags<C>(sb, wm, wn, lane, 1, fa[1], fb[1]);
+            mfma_step<C, NR>(fa[0], fb[0], acc);
+            // hand-over of unit u + 1 (pinned, as in run_direct_xt); after
+            // the last unit it still runs and reads an unused slot
+            __builtin_amdgcn_sched_barrier(0);
+            if (2 * u + 4 < nq)
+                wait_vmem_le<C::LPW>();
+            else
+                wait_vmem();
+            ring_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if (ragged && (qtail >> 1) == u + 1) {
+                fill_k_tail<C>(j, slot(g + qtail), qtail * C::BK, tid);
+                __syncthreads();
+            }
+            read_frags<C>(slot(g + 2 * u + 2), wm, wn, lane, 0, fa[0], fb[0]);
+            mfma_step<C, NR>(fa[1], fb[1], acc);
+            // the positions of unit u are free now
+            if (2 * u + 5 < nq)
+                issue_direct<C>(j, sa, (2 * u + 5) * C::BK, wave, lane);
+            if (2 * u + 6 < nq) pend = 2 * u + 6;
+        }
+        g += nq;
+        // slots 0 .. 2 of the next owned sub-tensor go to the three
+        // positions other than those of the last unit, then this one is
+        // stored
+        t += G;
+        const bool more = t < total;
+        Job nj;
+        if (more) {
+            nj = prov.job(t);
+            const int nq2 = nslots(nj);
+            for (int q = 0; q < 3 && q < nq2; ++q)
+                issue_direct<C>(nj, slot(g + q), q * C::BK, wave, lane);
+        }
+        epilogue<C>(j, wm, wn, lane, acc, nullptr);
+        if (!more) break;
+        j = nj;
+    }
+}
+
 // Register-staged programs (f32).
 template <class C, class P>
 __device__ __forceinline__ void run_regs(const P &prov, char *smem) {
@@ -1318,6 +1426,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_tiled_kernel(
     SingleProvider<C> p{g};
     if constexpr (C::PP)
         run_pingpong<C>(p, smem);
+    else if constexpr (C::XT && C::NS == 5)
+        run_direct_x5<C>(p, smem);
     else if constexpr (C::XT)
         run_direct_xt<C>(p, smem);
     else if constexpr (C::DIRECT)
@@ -1334,6 +1444,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_grouped_kernel(
     GroupProvider<C> p{tab, n, total, G};
     if constexpr (C::PP)
         run_pingpong<C>(p, smem);
+    else if constexpr (C::XT && C::NS == 5)
+        run_direct_x5<C>(p, smem);
     else if constexpr (C::XT)
         run_direct_xt<C>(p, smem);
     else if constexpr (C::DIRECT)
@@ -1403,6 +1515,8 @@ const VariantEntry *table(int *count) {
         TG_VARIANTS_PP(TG_BF16, 256, 256, 64, 4),
         TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 4),
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 4),
+        TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 5),
+        TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2, 128, 2),

@@ -516,6 +516,9 @@ def _operands(M, N, K, b_trans, gen_a, gen_b, dtype):
         return A, B, Ad, Bd
     A = gen_a((M, K))
     B = gen_b((N, K) if b_trans else (K, N))
+    if (K * A.element_size()) % 16:
+        # rows of K elements start on 16-byte boundaries
+        return A, B, dev_padded(A), dev_padded(B) if b_trans else dev(B)
     return A, B, dev(A), dev(B)
 
 
@@ -542,11 +545,14 @@ def _pick(C, rows):
 
 
 # (M, N, K): ragged M and N over several sub-tensors; K with a partial last
-# K tile; K = 0; and a grid of more sub-tensors than persistent programs,
-# so that programs own several each (the K-tile stream crosses sub-tensor
+# K tile; K = 0; K not a multiple of the 16-byte chunk (101, 77: the chunk
+# straddling K is filled element by element, in the first and in a later
+# hand-over); and a grid of more sub-tensors than persistent programs, so
+# that programs own several each (the K-tile stream crosses sub-tensor
 # boundaries).
 EVERY_SHAPES = [(300, 264, 136), (520, 600, 328), (200, 136, 0),
-                (4352, 4352, 72)]
+                (4352, 4352, 72), (300, 264, 101), (520, 136, 77),
+                (130, 264, 37)]
 
 
 @pytest.mark.parametrize("b_trans", [False, True])
