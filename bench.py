@@ -171,6 +171,25 @@ def copy_calibration(nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def library_reference(tg, n=8192, reps=10):
+    """The vendor library's bf16 GEMM (torch.matmul, i.e. hipBLASLt) on the
+    headline shape and layout, timed beside the library's default launch
+    of the same product: context for the roofline fraction, and a command
+    to profile both kernels in one run."""
+    g = torch.Generator(device="cpu").manual_seed(2)
+    A = torch.randn((n, n), generator=g).to(torch.bfloat16).cuda()
+    B = torch.randn((n, n), generator=g).to(torch.bfloat16).cuda()
+    C = torch.empty((n, n), device="cuda")
+    Bt = B.t()
+    out = {}
+    for name, fn in (("library", lambda: torch.matmul(A, Bt)),
+                     ("tile_gemm", lambda: tg.tile_gemm(
+                         A, B, C, 256, 256, b_trans=True, checked=False))):
+        ms = timed(fn, reps, reps)
+        out[name] = {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline_and_err(res, target_s):
     import oracle
     rng = np.random.default_rng(2)
@@ -317,6 +336,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--library-reference", action="store_true",
+                    help="only time the vendor bf16 GEMM beside the "
+                         "headline launch")
     ap.add_argument("--picker", action="store_true",
                     help="also run the learned-picker evaluation "
                          "(2000 training / 200 held-out shapes)")
@@ -332,6 +354,9 @@ def main():
         copy_calibration()
         return
     import paper_2606_15991_amd as tg
+    if args.library_reference:
+        library_reference(tg)
+        return
 
     res = bench_bf16_main(args, tg)
     extra = {"ms_unchecked_launch": res["ms_unchecked"]}
