@@ -197,6 +197,11 @@ struct Job {
     int64_t lda, ldb, ldc;
     int32_t M, N, K;
     int32_t m0, n0;
+    // Load streams of the sub-tensor, fixed for all its K tiles: first
+    // byte of its A rows (and of its B rows, or of its B columns in row 0
+    // for B stored K x N) and the bytes from there to the operand's end.
+    const char *a_row, *b_row;
+    int64_t a_rem, b_rem;
 };
 
 // ------------------------------------------------------------ tile loads
@@ -231,6 +236,15 @@ __device__ __forceinline__ i32x4 make_srd(const void *base, uint32_t bytes) {
     return d;
 }
 
+// LDS address of a generic pointer into the workgroup's LDS: its low 32
+// bits (the shared aperture occupies the high half of the flat address).
+// Taken directly rather than through an address-space cast, which would
+// add a null-pointer test to every load.
+__device__ __forceinline__ uint32_t lds_addr(const char *p) {
+    return __builtin_amdgcn_readfirstlane(
+        (int)static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p)));
+}
+
 // One 16-byte-per-lane load from buffer `srd` at byte offset `voff` into
 // LDS at dst + 16 * lane.  M0 holds the LDS address; one wait state
 // separates its write from the load.  The first load after `srd` was
@@ -239,9 +253,7 @@ __device__ __forceinline__ i32x4 make_srd(const void *base, uint32_t bytes) {
 template <bool FIRST>
 __device__ __forceinline__ void dma16(const i32x4 &srd, char *dst,
                                       uint32_t voff) {
-    const uint32_t lds = __builtin_amdgcn_readfirstlane(
-        (int)static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
-            (lds_void *)dst)));
+    const uint32_t lds = lds_addr(dst);
     if constexpr (FIRST)
         asm volatile(
             "s_nop 4\n\ts_mov_b32 m0, %0\n\ts_nop 0\n\t"
@@ -262,9 +274,7 @@ __device__ __forceinline__ void dma16(const i32x4 &srd, char *dst,
 // dma16).
 __device__ __forceinline__ void dma4(const i32x4 &srd, char *dst,
                                      uint32_t voff) {
-    const uint32_t lds = __builtin_amdgcn_readfirstlane(
-        (int)static_cast<uint32_t>(reinterpret_cast<uintptr_t>(
-            (lds_void *)dst)));
+    const uint32_t lds = lds_addr(dst);
     asm volatile(
         "s_nop 4\n\ts_mov_b32 m0, %0\n\ts_nop 0\n\t"
         "buffer_load_dword %1, %2, 0 offen lds"
@@ -277,6 +287,19 @@ __device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
     return b <= 0 ? 0u : (b >= 0x7fffffff ? 0x7fffffffu : (uint32_t)b);
 }
 
+template <class C>
+__device__ __forceinline__ void set_streams(Job &j) {
+    j.a_row = j.a + (int64_t)j.m0 * j.lda * C::ES;
+    j.a_rem = (int64_t)(j.M - j.m0) * j.lda * C::ES;
+    if constexpr (C::B_KMAJOR) {
+        j.b_row = j.b + (int64_t)j.n0 * C::ES;
+        j.b_rem = ((int64_t)j.K * j.ldb - j.n0) * C::ES;
+    } else {
+        j.b_row = j.b + (int64_t)j.n0 * j.ldb * C::ES;
+        j.b_rem = (int64_t)(j.N - j.n0) * j.ldb * C::ES;
+    }
+}
+
 // Direct HBM -> LDS issue of K tile k0 of one owned sub-tensor.  Each lane
 // fetches the 16-byte chunk that the LDS swizzle places at its position:
 // lane l of the 1 KiB block rb writes row rb * RPK + l / CPRW at chunk
@@ -284,13 +307,11 @@ __device__ __forceinline__ uint32_t sat_bytes(int64_t b) {
 // beyond M / N and chunks not wholly inside K read as zeros (out-of-range
 // buffer offsets); a chunk straddling K is filled by fill_k_tail.
 template <class C, int ROWS>
-__device__ __forceinline__ void issue_operand(const char *mat, int64_t ld,
-                                              int r0, int rows, int k0,
-                                              int K, char *dst, int wave,
-                                              int lane) {
-    const char *base = mat + ((int64_t)r0 * ld + k0) * C::ES;
-    const uint32_t nrec = sat_bytes(((int64_t)(rows - r0) * ld - k0) * C::ES);
-    const i32x4 srd = make_srd(base, nrec);
+__device__ __forceinline__ void issue_operand(const char *row0, int64_t rem,
+                                              int64_t ld, int k0, int K,
+                                              char *dst, int wave, int lane) {
+    const int64_t skip = (int64_t)k0 * C::ES;
+    const i32x4 srd = make_srd(row0 + skip, sat_bytes(rem - skip));
     const int rsub = lane / C::CPRW, p = lane % C::CPRW;
 #pragma unroll
     for (int i = 0; i < ROWS / C::RPK / C::NW; ++i) {
@@ -313,20 +334,18 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
                                              int k0, int wave, int lane,
                                              int parts = 3) {
     if (parts & 1)
-        issue_operand<C, C::BM>(j.a, j.lda, j.m0, j.M, k0, j.K, stage, wave,
-                                lane);
+        issue_operand<C, C::BM>(j.a_row, j.a_rem, j.lda, k0, j.K, stage,
+                                wave, lane);
     if (!(parts & 2)) return;
     char *Bs = stage + C::BM * C::RBY;
     if constexpr (!C::B_KMAJOR) {
-        issue_operand<C, C::BN>(j.b, j.ldb, j.n0, j.N, k0, j.K, Bs, wave,
-                                lane);
+        issue_operand<C, C::BN>(j.b_row, j.b_rem, j.ldb, k0, j.K, Bs,
+                                wave, lane);
     } else {
         // k-major B: descriptor from (k0, n0); rows k >= K are past its end,
         // columns >= N are masked per lane
-        const char *base = j.b + ((int64_t)k0 * j.ldb + j.n0) * C::ES;
-        const uint32_t nrec =
-            sat_bytes(((int64_t)(j.K - k0) * j.ldb - j.n0) * C::ES);
-        const i32x4 srd = make_srd(base, nrec);
+        const int64_t skip = (int64_t)k0 * j.ldb * C::ES;
+        const i32x4 srd = make_srd(j.b_row + skip, sat_bytes(j.b_rem - skip));
 #pragma unroll
         for (int i = 0; i < C::BK * C::RB / 1024 / C::NW; ++i) {
             const int gi = i * C::NW + wave;
@@ -1382,6 +1401,7 @@ struct SingleProvider {
         j.lda = g.lda; j.ldb = g.ldb; j.ldc = g.ldc;
         j.M = g.M; j.N = g.N; j.K = g.K;
         j.m0 = tm * C::BM; j.n0 = tn * C::BN;
+        set_streams<C>(j);
         return j;
     }
 };
@@ -1414,6 +1434,7 @@ struct GroupProvider {
         j.lda = pb.lda; j.ldb = pb.ldb; j.ldc = pb.ldc;
         j.M = pb.M; j.N = pb.N; j.K = pb.K;
         j.m0 = tm * C::BM; j.n0 = tn * C::BN;
+        set_streams<C>(j);
         return j;
     }
 };
