@@ -155,7 +155,7 @@ def bench_bf16_kn(args, tg):
     A = synth.to_bf16(synth.normal((n, n), 2)).cuda()
     B = synth.to_bf16(synth.normal((n, n), 202)).cuda()
     C = torch.empty((n, n), device="cuda")
-    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256), 20, 10)
+    ms = timed(lambda: tg.tile_gemm(A, B, C, 256, 256), 50, 100)
     return {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
 
 
@@ -193,7 +193,7 @@ def library_reference(tg, n=8192, reps=10):
 def cpu_baseline_and_err(res, target_s):
     import oracle
     rng = np.random.default_rng(2)
-    rows = rng.permutation(res["M"])[:512]
+    rows = rng.permutation(res["M"])[:4096]
     done, R, secs = oracle_rows(res["A"], res["Bt"], rows, b_nk=True,
                                 target_s=target_s)
     got = res["C"][done].astype(np.float64)
@@ -213,7 +213,7 @@ def bench_fp8(args, tg, n=8192):
     Ad, Bd, sad, sbd = qa.cuda(), qb.cuda(), sa.cuda(), sb.cuda()
     C = torch.empty((n, n), device="cuda")
     ms = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True,
-                                    scale_a=sad, scale_b=sbd), 20, 10)
+                                    scale_a=sad, scale_b=sbd), 50, 100)
     return {"M": n, "N": n, "K": n, "ms": ms,
             "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12,
             "frac_fp8_peak": 2.0 * n ** 3 / (ms * 1e-3) / 1e12 /
@@ -330,7 +330,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--quick", action="store_true",
                     help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)

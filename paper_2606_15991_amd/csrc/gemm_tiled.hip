@@ -860,8 +860,11 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
             compute_stage<C>(stage(g + kt), wm, wn, lane, acc,
                              [&](int kk, int KK) {
                 if (!nxt) return;
-                const int parts = (kk == 0 ? 1 : 0) |
-                                  (kk == (KK > 1 ? 1 : 0) ? 2 : 0);
+                // e4m3 K steps are twice as long: both at the first
+                const int parts =
+                    C::DTYPE == TG_FP8_E4M3
+                        ? (kk == 0 ? 3 : 0)
+                        : (kk == 0 ? 1 : 0) | (kk == (KK > 1 ? 1 : 0) ? 2 : 0);
                 if (parts)
                     issue_direct<C>(j, stage(g + kt + C::NS - 1),
                                     (kt + C::NS - 1) * C::BK, wave, lane,
