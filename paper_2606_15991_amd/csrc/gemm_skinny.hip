@@ -74,7 +74,11 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     // to row N - 1 and activation rows beyond M read row 0, and both only
     // feed outputs that are never stored.  A ragged K tail takes the checked
     // loads.
-    uint4 wv[1][UNROLL], xv[1][UNROLL][XV];
+    // Two register buffers (the wave's next super-step is loaded while the
+    // current one is contracted) where the register budget allows: up to
+    // 512 threads per program.
+    constexpr int NB = KS <= 8 ? 2 : 1;
+    uint4 wv[NB][UNROLL], xv[NB][UNROLL][XV];
     auto load_fast = [&](int s0, int b) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -119,9 +123,27 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     constexpr int STRIDE = KS * UNROLL;
     const int nfull = g.K / KSTEP;            // steps wholly inside K
     int s0 = wave * UNROLL;
-    for (; s0 + UNROLL <= nfull; s0 += STRIDE) {
-        load_fast(s0, 0);
-        contract(0);
+    if constexpr (NB == 2) {
+        bool have0 = s0 + UNROLL <= nfull;
+        if (have0) load_fast(s0, 0);
+        while (have0) {
+            const int s1 = s0 + STRIDE;
+            const bool have1 = s1 + UNROLL <= nfull;
+            if (have1) load_fast(s1, NB - 1);
+            contract(0);
+            s0 = s1;
+            if (!have1) break;
+            const int s2 = s1 + STRIDE;
+            have0 = s2 + UNROLL <= nfull;
+            if (have0) load_fast(s2, 0);
+            contract(NB - 1);
+            s0 = s2;
+        }
+    } else {
+        for (; s0 + UNROLL <= nfull; s0 += STRIDE) {
+            load_fast(s0, 0);
+            contract(0);
+        }
     }
     for (; s0 < nsteps; s0 += STRIDE) {       // ragged tail, bounds checked
         load_checked(s0, 0);

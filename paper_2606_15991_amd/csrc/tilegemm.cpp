@@ -343,10 +343,14 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
                         "(partition %d x %d)", 16, cfg.bm, cfg.bn);
         cfg.bm = 16;
         if (cfg.ksplit == 0) {
-            // enough wavefronts to keep every compute unit streaming
+            // four wavefronts per program split K (two for e4m3 weights over
+            // more than 1024 programs: their rows are half as long), and at
+            // least one wavefront per compute unit.  Measured on the decode
+            // shapes with cold weights, where each wavefront keeps two
+            // super-steps of loads in flight.
             int64_t progs = (p.N + 15) / 16;
-            int ks = 1;
-            while (ks < 16 && progs * ks < (int64_t)std::max(cus, 1) * 16)
+            int ks = (p.b_dt == TG_FP8_E4M3 && progs >= 1024) ? 2 : 4;
+            while (ks < 16 && progs * ks < (int64_t)std::max(cus, 1))
                 ks *= 2;
             cfg.ksplit = ks;
         }
