@@ -141,11 +141,25 @@ def bench_bf16_main(args, tg):
     ms_unchecked = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256,
                                               b_trans=True, checked=False),
                          max(args.steps // 2, 5), 2)
+    # per-launch durations (events between back-to-back launches) for the
+    # spread of the same workload
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(31)]
+    ev[0].record(s)
+    for i in range(30):
+        step()
+        ev[i + 1].record(s)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(30)])
+    spread = {"launches": 30, "p25_ms": float(np.percentile(per, 25)),
+              "median_ms": float(np.median(per)),
+              "p75_ms": float(np.percentile(per, 75))}
     step()
     torch.cuda.synchronize()
     Cc = C.cpu().numpy()
     res = {"M": M, "N": N, "K": K, "ms": ms, "tflops": tflops,
-           "ms_unchecked": ms_unchecked, "A": A, "Bt": Bt, "C": Cc}
+           "ms_unchecked": ms_unchecked, "spread": spread, "A": A, "Bt": Bt,
+           "C": Cc}
     return res
 
 
@@ -336,6 +350,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter scaling)")
+    ap.add_argument("--decode", action="store_true",
+                    help="only the decode-shaped products (one JSON line)")
     ap.add_argument("--library-reference", action="store_true",
                     help="only time the vendor bf16 GEMM beside the "
                          "headline launch")
@@ -357,9 +373,13 @@ def main():
     if args.library_reference:
         library_reference(tg)
         return
+    if args.decode:
+        print(json.dumps({"decode": bench_decode(args, tg)}), flush=True)
+        return
 
     res = bench_bf16_main(args, tg)
-    extra = {"ms_unchecked_launch": res["ms_unchecked"]}
+    extra = {"ms_unchecked_launch": res["ms_unchecked"],
+             "launch_spread": res["spread"]}
     if not args.quick:
         extra["fp8_8192"] = bench_fp8(args, tg)
         extra.update(bench_f32_and_split(args, tg))
