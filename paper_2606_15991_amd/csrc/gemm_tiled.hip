@@ -95,13 +95,20 @@ struct Cfg {
     static constexpr int SCALE_SLOT = (BM + BN) * 4;
     static constexpr int NSLOT = NS + 1;
     static constexpr int SMEM =
-        NS * STAGE + (DIRECT && SCH_ != TG_SCHED_CROSS ? NSLOT * SCALE_SLOT : 0);
+        (SCH_ == TG_SCHED_CROSS && NS == 3 ? 5 * (STAGE / 2) : NS * STAGE) +
+        (DIRECT && SCH_ != TG_SCHED_CROSS ? NSLOT * SCALE_SLOT : 0);
     static constexpr int LPW = STAGE / 1024 / NW;   // 1 KiB loads per wave
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
     static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
-    static_assert(NS == 2 || NS == 4 || (NS == 5 && SCH_ == TG_SCHED_CROSS &&
-                                         RBY == 64),
-                  "ring of 2 or 4 stages, or 5 of 64-byte rows");
+    static_assert(NS == 2 || NS == 4 ||
+                      (NS == 5 && SCH_ == TG_SCHED_CROSS && RBY == 64) ||
+                      (NS == 3 && SCH_ == TG_SCHED_CROSS && RBY == 128 &&
+                       BM == BN),
+                  "ring of 2 or 4 stages, 5 of 64-byte rows, or 5 operand "
+                  "halves (NS = 3)");
+    // NS = 3 with the cross-tile schedule: the LDS holds five operand
+    // tiles (A or B of one K tile each) instead of three whole stages.
+    static constexpr bool HALVES = SCH_ == TG_SCHED_CROSS && NS == 3;
     static_assert(DIRECT || (RBY == 128 && NS == 2), "f32 register path");
     static_assert((BM / RPK) % NW == 0, "A 1 KiB blocks per wave");
     static_assert(B_KMAJOR ? (BK * RB / 1024) % NW == 0
@@ -328,16 +335,18 @@ __device__ __forceinline__ void issue_operand(const char *row0, int64_t rem,
     }
 }
 
-// parts: bit 0 = the A tile, bit 1 = the B tile.
+// The A tile of K tile k0 into As.
 template <class C>
-__device__ __forceinline__ void issue_direct(const Job &j, char *stage,
-                                             int k0, int wave, int lane,
-                                             int parts = 3) {
-    if (parts & 1)
-        issue_operand<C, C::BM>(j.a_row, j.a_rem, j.lda, k0, j.K, stage,
-                                wave, lane);
-    if (!(parts & 2)) return;
-    char *Bs = stage + C::BM * C::RBY;
+__device__ __forceinline__ void issue_a(const Job &j, char *As, int k0,
+                                        int wave, int lane) {
+    issue_operand<C, C::BM>(j.a_row, j.a_rem, j.lda, k0, j.K, As, wave,
+                            lane);
+}
+
+// The B tile of K tile k0 into Bs.
+template <class C>
+__device__ __forceinline__ void issue_b(const Job &j, char *Bs, int k0,
+                                        int wave, int lane) {
     if constexpr (!C::B_KMAJOR) {
         issue_operand<C, C::BN>(j.b_row, j.b_rem, j.ldb, k0, j.K, Bs,
                                 wave, lane);
@@ -362,6 +371,15 @@ __device__ __forceinline__ void issue_direct(const Job &j, char *stage,
                 dma16<false>(srd, Bs + gi * 1024, voff);
         }
     }
+}
+
+// parts: bit 0 = the A tile, bit 1 = the B tile, into one stage.
+template <class C>
+__device__ __forceinline__ void issue_direct(const Job &j, char *stage,
+                                             int k0, int wave, int lane,
+                                             int parts = 3) {
+    if (parts & 1) issue_a<C>(j, stage, k0, wave, lane);
+    if (parts & 2) issue_b<C>(j, stage + C::BM * C::RBY, k0, wave, lane);
 }
 
 // Scales of one owned sub-tensor into its LDS slot: scale_a[m0 .. m0+BM)
@@ -746,8 +764,8 @@ __device__ __forceinline__ void zero_acc(f32x16 (&acc)[C::FM][C::FN]) {
 // stored N x K) into LDS one by one.  Called after the stage's loads have
 // landed and all wavefronts passed a barrier; a barrier must follow.
 template <class C>
-__device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
-                                            int tid) {
+__device__ __forceinline__ void fill_k_tail2(const Job &j, char *stage,
+                                             char *Bs, int k0, int tid) {
     const int rem = j.K % C::EPC;
     const int kbase = j.K - rem;                  // first element of the chunk
     const int chunk = (kbase - k0) / C::EPC;      // its logical chunk index
@@ -765,7 +783,6 @@ __device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
         }
     }
     if constexpr (!C::B_KMAJOR) {
-        char *Bs = stage + C::BM * C::RBY;
         for (int r = tid; r < C::BN; r += C::THREADS) {
             const int row = j.n0 + r;
             char *dst = Bs + swz<C>(r, chunk);
@@ -782,6 +799,12 @@ __device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
             }
         }
     }
+}
+
+template <class C>
+__device__ __forceinline__ void fill_k_tail(const Job &j, char *stage, int k0,
+                                            int tid) {
+    fill_k_tail2<C>(j, stage, stage + C::BM * C::RBY, k0, tid);
 }
 
 // ------------------------------------------------------- persistent loops
@@ -894,12 +917,10 @@ __device__ __forceinline__ void run_direct(const P &prov, char *smem) {
 // bf16 fragments of K step kk of a stage: FM A fragments (rows
 // wm * TM + f * 32 + lane % 32) and FN B fragments, eight k each.
 template <class C>
-__device__ __forceinline__ void read_frags(const char *stage, int wm, int wn,
-                                           int lane, int kk,
-                                           i32x4 (&af)[C::FM],
-                                           i32x4 (&bf)[C::FN]) {
-    const char *As = stage;
-    const char *Bs = stage + C::BM * C::RBY;
+__device__ __forceinline__ void read_frags2(const char *As, const char *Bs,
+                                            int wm, int wn, int lane, int kk,
+                                            i32x4 (&af)[C::FM],
+                                            i32x4 (&bf)[C::FN]) {
     const int r = lane & 31, half = lane >> 5;
     const int co = ((2 * kk + half) ^ swz_f<C>(r)) << 4;
     const char *Aw = As + wm * C::TM * C::RBY + r * C::RBY + co;
@@ -914,6 +935,14 @@ __device__ __forceinline__ void read_frags(const char *stage, int wm, int wn,
             bf[f] = *reinterpret_cast<const i32x4 *>(
                 Bs + (wn * C::TN + f * 32 + r) * C::RBY + co);
     }
+}
+
+template <class C>
+__device__ __forceinline__ void read_frags(const char *stage, int wm, int wn,
+                                           int lane, int kk,
+                                           i32x4 (&af)[C::FM],
+                                           i32x4 (&bf)[C::FN]) {
+    read_frags2<C>(stage, stage + C::BM * C::RBY, wm, wn, lane, kk, af, bf);
 }
 
 // The MFMAs of one K step, with the fragment reads issued just before
@@ -1134,6 +1163,113 @@ __device__ __forceinline__ void run_direct_x5(const P &prov, char *smem) {
             const int nq2 = nslots(nj);
             for (int q = 0; q < 3 && q < nq2; ++q)
                 issue_direct<C>(nj, slot(g + q), q * C::BK, wave, lane);
+        }
+        epilogue<C>(j, wm, wn, lane, acc, nullptr);
+        if (!more) break;
+        j = nj;
+    }
+}
+
+// Cross-tile schedule over five operand slots (bf16, 64-deep K tiles,
+// BM = BN): each slot holds the A or the B tile of one K tile, so the
+// 160 KiB of LDS hold two and a half K tiles.  Operand q of a sub-tensor
+// (A of tile t is q = 2t, B is q = 2t + 1; running index g + q) lives in
+// slot (g + q) % 5.  At the hand-over of tile kt + 1 (before the last K
+// step of tile kt) the slots of tile kt are freed: the B tile of kt + 2
+// goes into one right away and the A tile of kt + 3 into the other after
+// the next tile's first K step, so that A tiles are in flight for about
+// two tile periods and B tiles for about one (two-stage ring: one and a
+// bit less).  The hand-over waits for tile kt + 1 while the A tile of
+// kt + 2, issued last, may still be in flight.
+template <class C, class P>
+__device__ __forceinline__ void run_direct_xh(const P &prov, char *smem) {
+    static_assert(C::HALVES && C::BM == C::BN, "five operand slots");
+    constexpr int KK = C::BK / 16;
+    constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
+    constexpr int HALF = C::STAGE / 2;
+    constexpr int LPA = C::BM * C::RBY / 1024 / C::NW;  // loads per A tile
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    int t = program_slot(blockIdx.x, G);
+    if (t >= total) return;
+    auto slot = [&](int q) { return smem + (q % 5) * HALF; };
+    Job j = prov.job(t);
+    int g = 0;
+    {
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        if (nk > 0) {
+            issue_a<C>(j, slot(g), 0, wave, lane);
+            issue_b<C>(j, slot(g + 1), 0, wave, lane);
+        }
+        if (nk > 1) issue_a<C>(j, slot(g + 2), C::BK, wave, lane);
+    }
+    f32x16 acc[C::FM][C::FN];
+    i32x4 fa[2][C::FM], fb[2][C::FN];
+    while (true) {
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        const bool ragged = (j.K % C::EPC) != 0;
+        zero_acc<C>(acc);
+        wait_vmem();          // also covers the previous sub-tensor's stores
+        ring_barrier();
+        if (nk > 0) {
+            if (ragged && nk == 1) {
+                fill_k_tail2<C>(j, slot(g), slot(g + 1), 0, tid);
+                __syncthreads();
+            }
+            // the slots of the previous sub-tensor's last tile are free
+            if (nk > 1) issue_b<C>(j, slot(g + 3), C::BK, wave, lane);
+            read_frags2<C>(slot(g), slot(g + 1), wm, wn, lane, 0, fa[0],
+                           fb[0]);
+        }
+        for (int kt = 0; kt < nk; ++kt) {
+            const char *sa = slot(g + 2 * kt), *sb = slot(g + 2 * kt + 1);
+#pragma unroll
+            for (int kk = 0; kk < KK - 1; ++kk) {
+                const int s = kk & 1;
+                read_frags2<C>(sa, sb, wm, wn, lane, kk + 1, fa[s ^ 1],
+                               fb[s ^ 1]);
+                mfma_step<C, NR>(fa[s], fb[s], acc);
+                if (kk == 0 && kt + 2 < nk)   // into the slot of B of kt - 1
+                    issue_a<C>(j, slot(g + 2 * kt + 4), (kt + 2) * C::BK,
+                               wave, lane);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (kt + 2 < nk)
+                wait_vmem_le<LPA>();
+            else
+                wait_vmem();
+            ring_barrier();
+            __builtin_amdgcn_sched_barrier(0);
+            if (ragged && kt + 1 == nk - 1) {
+                fill_k_tail2<C>(j, slot(g + 2 * kt + 2), slot(g + 2 * kt + 3),
+                                (kt + 1) * C::BK, tid);
+                __syncthreads();
+            }
+            read_frags2<C>(slot(g + 2 * kt + 2), slot(g + 2 * kt + 3), wm, wn,
+                           lane, 0, fa[0], fb[0]);
+            mfma_step<C, NR>(fa[1], fb[1], acc);
+            if (kt + 2 < nk)                  // into the slot of A of kt
+                issue_b<C>(j, slot(g + 2 * kt + 5), (kt + 2) * C::BK, wave,
+                           lane);
+        }
+        g += 2 * nk;
+        // A and B of the next sub-tensor's first tile and its second A go
+        // to the three slots other than those of the last tile, then this
+        // one is stored
+        t += G;
+        const bool more = t < total;
+        Job nj;
+        if (more) {
+            nj = prov.job(t);
+            const int nk2 = (nj.K + C::BK - 1) / C::BK;
+            if (nk2 > 0) {
+                issue_a<C>(nj, slot(g), 0, wave, lane);
+                issue_b<C>(nj, slot(g + 1), 0, wave, lane);
+            }
+            if (nk2 > 1) issue_a<C>(nj, slot(g + 2), C::BK, wave, lane);
         }
         epilogue<C>(j, wm, wn, lane, acc, nullptr);
         if (!more) break;
@@ -1452,6 +1588,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_tiled_kernel(
         run_pingpong<C>(p, smem);
     else if constexpr (C::XT && C::NS == 5)
         run_direct_x5<C>(p, smem);
+    else if constexpr (C::HALVES)
+        run_direct_xh<C>(p, smem);
     else if constexpr (C::XT)
         run_direct_xt<C>(p, smem);
     else if constexpr (C::DIRECT)
@@ -1470,6 +1608,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_grouped_kernel(
         run_pingpong<C>(p, smem);
     else if constexpr (C::XT && C::NS == 5)
         run_direct_x5<C>(p, smem);
+    else if constexpr (C::HALVES)
+        run_direct_xh<C>(p, smem);
     else if constexpr (C::XT)
         run_direct_xt<C>(p, smem);
     else if constexpr (C::DIRECT)
@@ -1539,6 +1679,8 @@ const VariantEntry *table(int *count) {
         TG_VARIANTS_PP(TG_BF16, 256, 256, 64, 4),
         TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 4),
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 4),
+        TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 128, 3),
+        TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 128, 3),
         TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
