@@ -131,7 +131,8 @@ typedef enum tg_sched {
                               multiple of 16 bytes of the operand type      */
     TG_SCHED_CROSS = 3     /* lock-step with the hand-over barrier of the
                               next K tile placed before the last K step of
-                              the current one (bf16)                        */
+                              the current one (bf16); the default for B
+                              stored N x K                                  */
 } tg_sched;
 
 typedef struct tg_config {
@@ -139,7 +140,9 @@ typedef struct tg_config {
     int32_t bm, bn, bk;
     int32_t wm, wn;
     int32_t ksplit;       /* skinny kernel: wavefronts sharing one tile's K  */
-    int32_t stages;       /* tiled kernel: LDS stages of the K-tile ring     */
+    int32_t stages;       /* tiled kernel: LDS stages of the K-tile ring;
+                             with TG_SCHED_CROSS, 3 means five slots of one
+                             operand tile each (A or B of a K tile)         */
     int32_t sched;        /* tiled kernel: tg_sched                          */
 } tg_config;
 
