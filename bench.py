@@ -361,7 +361,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
-              "supported by this single-GPU build", file=sys.stderr)
+              "supported: the benchmark runs on a single GPU", file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)

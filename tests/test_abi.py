@@ -280,3 +280,42 @@ def test_picker_features_describe_the_configuration():
         seen.add(tuple(f))
     # every candidate is distinguishable by its features
     assert len(seen) == len(tg.tile_gemm_candidates(A, B, C, b_trans=True))
+
+
+def test_decode_split_default():
+    """Without a GPU the plan still resolves the decode kernel's K split:
+    four wavefronts per program, two for e4m3 weights over more than 1024
+    programs."""
+    for wdt, N, want in ((torch.bfloat16, 5120, 4), (torch.bfloat16, 51200, 4),
+                         (torch.float8_e4m3fn, 5120, 4),
+                         (torch.float8_e4m3fn, 51200, 2)):
+        x = torch.empty((1, 5120), dtype=torch.bfloat16)
+        W = torch.empty((N, 5120), dtype=wdt)
+        y = torch.empty((1, N), dtype=torch.bfloat16)
+        cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
+        assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["ksplit"] == want, \
+            (wdt, N, cfg)
+
+
+def test_bench_measures_one_gpu_only():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"),
+                        "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_traffic_only_for_the_profiled_sources(monkeypatch):
+    """bench.py reports the profiled HBM traffic only while the kernel
+    sources hash to the value recorded beside it."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    text = open(os.path.join(ROOT, bench.TRAFFIC_PROFILE)).read()
+    sha = re.search(r"kernel_source_sha256: (\w+)", text).group(1)
+    nbytes = int(re.search(r"traffic_bytes_per_launch: (\d+)", text).group(1))
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: sha)
+    assert bench.traffic_from_profile() == nbytes
+    monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 64)
+    assert bench.traffic_from_profile() is None
