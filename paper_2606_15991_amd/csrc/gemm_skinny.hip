@@ -3,10 +3,11 @@
 // of W, i.e. per output column).
 //
 // The work is bound by streaming W from HBM once (arithmetic intensity about
-// M flop per weight byte).  One tile program owns the 16 output columns
-// n0 .. n0+15 for all M rows; its KS wavefronts split K between them and
-// stream their share of the 16 weight rows with 16-byte loads, several in
-// flight per lane.  The contraction runs on the 16x16x32 bf16 matrix
+// M flop per weight byte).  One tile program owns 16 or 32 output columns
+// (RT row tiles of 16 weight rows) for all M rows; its KS wavefronts split
+// K between them and stream their share of the weight rows with 16-byte
+// loads, several in flight per lane.  With two row tiles every activation
+// chunk loaded serves two weight chunks.  The contraction runs on the 16x16x32 bf16 matrix
 // instruction with the weight rows as the A operand and the (zero-padded)
 // activation rows as the B operand; E4M3 weights are decoded exactly to
 // bf16 in registers first (there is no mixed bf16 x e4m3 matrix
@@ -19,7 +20,6 @@
 namespace tg {
 namespace {
 
-constexpr int UNROLL = 8;
 
 // 16 bytes at p of which only the first n (0..16) are inside the operand;
 // the rest read as zero.  Used for the one chunk per row that straddles K.
@@ -40,28 +40,36 @@ __device__ __forceinline__ uint4 ld_chunk(const char *row, int k, int K,
     return uint4{0, 0, 0, 0};
 }
 
-template <int WDT, int KS, bool CBF16>
+template <int WDT, int KS, bool CBF16, int RT>
 __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     // Elements of K covered by one 16-byte weight load per lane group:
     // bf16: 8 per lane, 4 lane groups -> 32;  e4m3: 16 per lane -> 64.
     constexpr int EPL = WDT == TG_BF16 ? 8 : 16;
     constexpr int KSTEP = 4 * EPL;
-    __shared__ f32x4 part[KS][64];
+    // K steps per super-step: eight weight loads per lane either way
+    constexpr int UNROLL = 8 / RT;
+    __shared__ f32x4 part[KS][RT][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n0 = blockIdx.x * 16;
+    const int n0 = blockIdx.x * 16 * RT;
     const int r = lane & 15, grp = lane >> 4;
-    int wrow = n0 + r;
-    wrow = wrow < g.N ? wrow : g.N - 1;
     const bool xrow_ok = r < g.M;
     const int xrow = xrow_ok ? r : 0;
 
-    const char *W = static_cast<const char *>(g.w) +
-                    (int64_t)wrow * g.ldw * (WDT == TG_BF16 ? 2 : 1);
+    const char *W[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+        int wrow = n0 + 16 * t + r;
+        wrow = wrow < g.N ? wrow : g.N - 1;
+        W[t] = static_cast<const char *>(g.w) +
+               (int64_t)wrow * g.ldw * (WDT == TG_BF16 ? 2 : 1);
+    }
     const uint16_t *X = static_cast<const uint16_t *>(g.x) +
                         (int64_t)xrow * g.ldx;
 
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nsteps = (g.K + KSTEP - 1) / KSTEP;
     constexpr int WES = WDT == TG_BF16 ? 2 : 1;
     constexpr int XV = WDT == TG_BF16 ? 1 : 2;   // activation chunks per step
@@ -78,12 +86,14 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     // current one is contracted) where the register budget allows: up to
     // 512 threads per program.
     constexpr int NB = KS <= 8 ? 2 : 1;
-    uint4 wv[NB][UNROLL], xv[NB][UNROLL][XV];
+    uint4 wv[NB][UNROLL][RT], xv[NB][UNROLL][XV];
     auto load_fast = [&](int s0, int b) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int k = (s0 + u) * KSTEP + grp * EPL;
-            wv[b][u] = ld16(W + (int64_t)k * WES);
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                wv[b][u][t] = ld16(W[t] + (int64_t)k * WES);
 #pragma unroll
             for (int c = 0; c < XV; ++c)
                 xv[b][u][c] = ld16(Xc + (int64_t)(k + 8 * c) * 2);
@@ -94,7 +104,10 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
         for (int u = 0; u < UNROLL; ++u) {
             const int k = (s0 + u) * KSTEP + grp * EPL;
             const bool live = s0 + u < nsteps;
-            wv[b][u] = live ? ld_chunk(W, k, g.K, EPL, WES) : uint4{0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                wv[b][u][t] = live ? ld_chunk(W[t], k, g.K, EPL, WES)
+                                   : uint4{0, 0, 0, 0};
             const bool ok = live && k < g.K;
 #pragma unroll
             for (int c = 0; c < XV; ++c)
@@ -104,21 +117,26 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     };
     auto contract = [&](int b) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u) {
-            if constexpr (WDT == TG_BF16) {
-                acc = mfma16_bf16(__builtin_bit_cast(i32x4, wv[b][u]),
-                                  __builtin_bit_cast(i32x4, xv[b][u][0]), acc);
-            } else {
-                uint2 w01 = e4m3x4_to_bf16x4(wv[b][u].x);
-                uint2 w23 = e4m3x4_to_bf16x4(wv[b][u].y);
-                uint2 w45 = e4m3x4_to_bf16x4(wv[b][u].z);
-                uint2 w67 = e4m3x4_to_bf16x4(wv[b][u].w);
-                i32x4 wa = {(int)w01.x, (int)w01.y, (int)w23.x, (int)w23.y};
-                i32x4 wb = {(int)w45.x, (int)w45.y, (int)w67.x, (int)w67.y};
-                acc = mfma16_bf16(wa, __builtin_bit_cast(i32x4, xv[b][u][0]), acc);
-                acc = mfma16_bf16(wb, __builtin_bit_cast(i32x4, xv[b][u][1]), acc);
+        for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                if constexpr (WDT == TG_BF16) {
+                    acc[t] = mfma16_bf16(
+                        __builtin_bit_cast(i32x4, wv[b][u][t]),
+                        __builtin_bit_cast(i32x4, xv[b][u][0]), acc[t]);
+                } else {
+                    uint2 w01 = e4m3x4_to_bf16x4(wv[b][u][t].x);
+                    uint2 w23 = e4m3x4_to_bf16x4(wv[b][u][t].y);
+                    uint2 w45 = e4m3x4_to_bf16x4(wv[b][u][t].z);
+                    uint2 w67 = e4m3x4_to_bf16x4(wv[b][u][t].w);
+                    i32x4 wa = {(int)w01.x, (int)w01.y, (int)w23.x, (int)w23.y};
+                    i32x4 wb = {(int)w45.x, (int)w45.y, (int)w67.x, (int)w67.y};
+                    acc[t] = mfma16_bf16(
+                        wa, __builtin_bit_cast(i32x4, xv[b][u][0]), acc[t]);
+                    acc[t] = mfma16_bf16(
+                        wb, __builtin_bit_cast(i32x4, xv[b][u][1]), acc[t]);
+                }
             }
-        }
     };
     constexpr int STRIDE = KS * UNROLL;
     const int nfull = g.K / KSTEP;            // steps wholly inside K
@@ -150,69 +168,81 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
         contract(0);
     }
 
-    part[wave][lane] = acc;
+#pragma unroll
+    for (int t = 0; t < RT; ++t) part[wave][t][lane] = acc[t];
     __syncthreads();
     if (wave != 0) return;
-    f32x4 s = part[0][lane];
-#pragma unroll
-    for (int w = 1; w < KS; ++w) {
-        f32x4 p = part[w][lane];
-        s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] += p[3];
-    }
     // 16 x 16 result layout: lane l, register v holds row 4 * (l / 16) + v
     // (a weight row, i.e. output column) and column l % 16 (an output row).
     const int m = lane & 15;
     if (m >= g.M) return;
     const float sa = g.scale_a ? g.scale_a[m] : 1.0f;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int n = n0 + 4 * grp + v;
-        if (n < g.N) {
-            float y = s[v] * sa;
-            if (g.scale_w) y *= g.scale_w[n];
-            int64_t off = (int64_t)m * g.ldy + n;
-            if constexpr (CBF16)
-                static_cast<uint16_t *>(g.y)[off] = f32_to_bf16_bits(y);
-            else
-                static_cast<float *>(g.y)[off] = y;
-            if (g.wcount) atomicAdd(&g.wcount[(int64_t)m * g.N + n], 1);
+    for (int t = 0; t < RT; ++t) {
+        f32x4 s = part[0][t][lane];
+#pragma unroll
+        for (int w = 1; w < KS; ++w) {
+            f32x4 p = part[w][t][lane];
+            s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] += p[3];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = n0 + 16 * t + 4 * grp + v;
+            if (n < g.N) {
+                float y = s[v] * sa;
+                if (g.scale_w) y *= g.scale_w[n];
+                int64_t off = (int64_t)m * g.ldy + n;
+                if constexpr (CBF16)
+                    static_cast<uint16_t *>(g.y)[off] = f32_to_bf16_bits(y);
+                else
+                    static_cast<float *>(g.y)[off] = y;
+                if (g.wcount) atomicAdd(&g.wcount[(int64_t)m * g.N + n], 1);
+            }
         }
     }
 }
 
-template <int WDT, int KS>
+template <int WDT, int KS, int RT>
 hipError_t launch_ks(int c_bf16, const SkinnyArgs &a, hipStream_t st) {
-    dim3 grid((a.N + 15) / 16), block(KS * 64);
+    dim3 grid((a.N + 16 * RT - 1) / (16 * RT)), block(KS * 64);
     if (c_bf16)
-        hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, true>), grid, block,
-                           0, st, a);
+        hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, true, RT>), grid,
+                           block, 0, st, a);
     else
-        hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, false>), grid, block,
-                           0, st, a);
+        hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, false, RT>), grid,
+                           block, 0, st, a);
     return hipGetLastError();
 }
 
-template <int WDT>
+template <int WDT, int RT>
 hipError_t launch_w(int c_bf16, int ksplit, const SkinnyArgs &a,
                     hipStream_t st) {
     switch (ksplit) {
-    case 1: return launch_ks<WDT, 1>(c_bf16, a, st);
-    case 2: return launch_ks<WDT, 2>(c_bf16, a, st);
-    case 4: return launch_ks<WDT, 4>(c_bf16, a, st);
-    case 8: return launch_ks<WDT, 8>(c_bf16, a, st);
-    case 16: return launch_ks<WDT, 16>(c_bf16, a, st);
+    case 1: return launch_ks<WDT, 1, RT>(c_bf16, a, st);
+    case 2: return launch_ks<WDT, 2, RT>(c_bf16, a, st);
+    case 4: return launch_ks<WDT, 4, RT>(c_bf16, a, st);
+    case 8: return launch_ks<WDT, 8, RT>(c_bf16, a, st);
+    case 16: return launch_ks<WDT, 16, RT>(c_bf16, a, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int WDT>
+hipError_t launch_bn(int c_bf16, int bn, int ksplit, const SkinnyArgs &a,
+                     hipStream_t st) {
+    if (bn == 16) return launch_w<WDT, 1>(c_bf16, ksplit, a, st);
+    if (bn == 32) return launch_w<WDT, 2>(c_bf16, ksplit, a, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
 
 hipError_t launch_skinny(int w_dtype, int c_bf16, int bn, int ksplit,
                          const SkinnyArgs &a, hipStream_t st) {
-    if (bn != 16) return hipErrorInvalidValue;
-    if (w_dtype == TG_BF16) return launch_w<TG_BF16>(c_bf16, ksplit, a, st);
+    if (w_dtype == TG_BF16)
+        return launch_bn<TG_BF16>(c_bf16, bn, ksplit, a, st);
     if (w_dtype == TG_FP8_E4M3)
-        return launch_w<TG_FP8_E4M3>(c_bf16, ksplit, a, st);
+        return launch_bn<TG_FP8_E4M3>(c_bf16, bn, ksplit, a, st);
     return hipErrorInvalidValue;
 }
 

@@ -317,7 +317,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
     bool s_ok = np == 1 && skinny_ok(p, A, B);
     if (cfg.kind == TG_KIND_AUTO) {
         if (s_ok && (cfg.bm == 0 || (cfg.bm >= p.M && cfg.bm <= 16)) &&
-            (cfg.bn == 0 || cfg.bn == 16))
+            (cfg.bn == 0 || cfg.bn == 16 || cfg.bn == 32))
             cfg.kind = TG_KIND_SKINNY;
         else if (t_ok && (cfg.bm == 0 ||
                           find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm,
@@ -336,20 +336,26 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
                         "decode kernel needs M <= 16, bf16 A, bf16/e4m3 B "
                         "stored N x K, aligned 16-byte rows");
         if (cfg.bm == 0) cfg.bm = 16;
-        if (cfg.bn == 0) cfg.bn = 16;
-        if (cfg.bm < p.M || cfg.bm > 16 || cfg.bn != 16)
+        if (cfg.bn == 0) {
+            // 32-column programs (each activation chunk serves two weight
+            // rows) for long rows and for long sweeps of e4m3 weights;
+            // measured on the decode shapes with cold weights
+            const bool wide = p.K >= 16384 ||
+                              (p.b_dt == TG_FP8_E4M3 && (p.N + 15) / 16 >= 1024);
+            cfg.bn = wide ? 32 : 16;
+        }
+        if (cfg.bm < p.M || cfg.bm > 16 || (cfg.bn != 16 && cfg.bn != 32))
             return fail(TG_E_UNSUPPORTED,
-                        "decode kernel owns %d-row x 16-column sub-tensors "
-                        "(partition %d x %d)", 16, cfg.bm, cfg.bn);
+                        "decode kernel owns 16-row x 16- or 32-column "
+                        "sub-tensors (partition %d x %d)", cfg.bm, cfg.bn);
         cfg.bm = 16;
         if (cfg.ksplit == 0) {
-            // four wavefronts per program split K (two for e4m3 weights over
-            // more than 1024 programs: their rows are half as long), and at
-            // least one wavefront per compute unit.  Measured on the decode
-            // shapes with cold weights, where each wavefront keeps two
-            // super-steps of loads in flight.
-            int64_t progs = (p.N + 15) / 16;
-            int ks = (p.b_dt == TG_FP8_E4M3 && progs >= 1024) ? 2 : 4;
+            // four wavefronts per program split K, and at least one
+            // wavefront per compute unit.  Measured on the decode shapes
+            // with cold weights, where each wavefront keeps two super-steps
+            // of loads in flight.
+            int64_t progs = (p.N + cfg.bn - 1) / cfg.bn;
+            int ks = 4;
             while (ks < 16 && progs * ks < (int64_t)std::max(cus, 1))
                 ks *= 2;
             cfg.ksplit = ks;
@@ -362,7 +368,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         cfg.wm = 1;
         cfg.wn = 1;
         L.s.tiles_m = 1;
-        L.s.tiles_n = (int32_t)((p.N + 15) / 16);
+        L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
         L.s.n_tiles = L.s.tiles_n;
         L.s.n_prog = L.s.n_tiles;
         L.s.group_m = 1;
@@ -444,12 +450,14 @@ void candidates(const Problem &p, const tg_in *A, const tg_in *B,
     const int np = p.precision == TG_PREC_BF16X3 ? 3
                    : p.precision == TG_PREC_BF16X6 ? 6 : 1;
     const int gdt = np > 1 ? TG_BF16 : p.a_dt;
-    for (int ks : {1, 2, 4, 8, 16}) {
-        tg_config c{};
-        c.kind = TG_KIND_SKINNY;
-        c.ksplit = ks;
-        try_cfg(c);
-    }
+    for (int bn : {16, 32})
+        for (int ks : {1, 2, 4, 8, 16}) {
+            tg_config c{};
+            c.kind = TG_KIND_SKINNY;
+            c.bn = bn;
+            c.ksplit = ks;
+            try_cfg(c);
+        }
     const int n = tiled_variant_count();
     for (int i = 0; i < n; ++i) {
         const TiledVariant &v = tiled_variant(i);
@@ -683,8 +691,8 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
         a.scale_a = sa; a.scale_w = sb; a.wcount = wc;
         a.ldx = A->ld; a.ldw = B->ld; a.ldy = C->ld;
         a.M = (int32_t)p.M; a.N = (int32_t)p.N; a.K = (int32_t)p.K;
-        a.bn = 16;
-        e = launch_skinny(p.b_dt, p.c_bf16, 16, L.cfg.ksplit, a, hs);
+        a.bn = L.cfg.bn;
+        e = launch_skinny(p.b_dt, p.c_bf16, L.cfg.bn, L.cfg.ksplit, a, hs);
         return e == hipSuccess ? TG_OK : hip_fail(e, "decode kernel launch");
     }
     if (L.cfg.kind == TG_KIND_SIMPLE) {

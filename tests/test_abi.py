@@ -189,7 +189,9 @@ def test_plan_decode_and_simple_kinds():
     y = torch.empty((1, 51200), dtype=torch.bfloat16)
     cfg, n_prog, _, _ = tg.tile_gemm_plan(x, w, y, b_trans=True,
                                           want_map=False)
-    assert cfg["kind"] == tg.TG_KIND_SKINNY and n_prog == 3200
+    # 32-column programs by default for this long e4m3 sweep
+    assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["bn"] == 32
+    assert n_prog == 1600
     # K not a multiple of 8 bf16 elements -> no vector loads -> simple kernel
     cfg, n_prog, offs, tiles = _plan(100, 90, 37)
     assert cfg["kind"] == tg.TG_KIND_SIMPLE and n_prog == 2 * 2
@@ -282,19 +284,22 @@ def test_picker_features_describe_the_configuration():
     assert len(seen) == len(tg.tile_gemm_candidates(A, B, C, b_trans=True))
 
 
-def test_decode_split_default():
-    """Without a GPU the plan still resolves the decode kernel's K split:
-    four wavefronts per program, two for e4m3 weights over more than 1024
-    programs."""
-    for wdt, N, want in ((torch.bfloat16, 5120, 4), (torch.bfloat16, 51200, 4),
-                         (torch.float8_e4m3fn, 5120, 4),
-                         (torch.float8_e4m3fn, 51200, 2)):
-        x = torch.empty((1, 5120), dtype=torch.bfloat16)
-        W = torch.empty((N, 5120), dtype=wdt)
+def test_decode_default_configuration():
+    """Without a GPU the plan still resolves the decode kernel's defaults:
+    four wavefronts split K; 32-column programs for rows of 16384 or more
+    and for e4m3 weights over more than 1024 16-column programs."""
+    for wdt, N, K, bn in ((torch.bfloat16, 5120, 5120, 16),
+                          (torch.bfloat16, 51200, 5120, 16),
+                          (torch.bfloat16, 5120, 25600, 32),
+                          (torch.float8_e4m3fn, 5120, 5120, 16),
+                          (torch.float8_e4m3fn, 51200, 5120, 32),
+                          (torch.float8_e4m3fn, 5120, 25600, 32)):
+        x = torch.empty((1, K), dtype=torch.bfloat16)
+        W = torch.empty((N, K), dtype=wdt)
         y = torch.empty((1, N), dtype=torch.bfloat16)
         cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
-        assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["ksplit"] == want, \
-            (wdt, N, cfg)
+        assert (cfg["kind"], cfg["bn"], cfg["ksplit"]) == \
+            (tg.TG_KIND_SKINNY, bn, 4), (wdt, N, K, cfg)
 
 
 def test_bench_measures_one_gpu_only():

@@ -495,6 +495,39 @@ def test_decode_ragged_k(M, K, wdt):
     assert rel_err(C.cpu(), reference(x, W, True, None, s)) <= 1e-5
 
 
+@pytest.mark.parametrize("M,N,K", [(1, 200, 1000), (8, 1040, 4096),
+                                   (16, 80, 512), (3, 72, 1001)])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+def test_every_decode_variant(M, N, K, wdt):
+    """Every decode configuration (16- or 32-column programs, every K split)
+    within the binary32 bar against the oracle, each element stored once."""
+    if wdt == "fp8" and K % 16:
+        K += 16 - K % 16
+    x = synth.to_bf16(synth.normal((M, K), 47))
+    w = synth.normal((N, K), 48, std=0.02)
+    if wdt == "bf16":
+        W, s = synth.to_bf16(w), None
+    else:
+        W, s = synth.quant_e4m3_rows(w)
+    xd, Wd = dev_padded(x), dev_padded(W)
+    sd = None if s is None else dev(s)
+    R = reference(x, W, True, None, s)
+    C = torch.empty((M, N), device=DEV)
+    cfgs = [c for c in tg.tile_gemm_candidates(xd, Wd, C, b_trans=True)
+            if c["kind"] == tg.TG_KIND_SKINNY]
+    assert sorted({c["bn"] for c in cfgs}) == [16, 32]
+    for cfg in cfgs:
+        note("every decode", M, N, K, wdt, cfg)
+        C.fill_(float("nan"))
+        wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+        tg.tile_gemm(xd, Wd, C, b_trans=True, scale_b=sd, config=cfg,
+                     write_count=wc)
+        torch.cuda.synchronize()
+        assert tuple(tg.tile_gemm.last_partition) == (16, cfg["bn"])
+        assert torch.all(wc == 1), cfg
+        assert rel_err(C.cpu(), R) <= 1e-5, cfg
+
+
 # ------------------------------------------------ every tiled instantiation
 
 def _tiled_configs(A, B, C, b_trans):
