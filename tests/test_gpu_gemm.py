@@ -390,6 +390,42 @@ def test_grouped_matches_oracle_and_single_launches():
             assert torch.equal(c, e), rep
 
 
+@pytest.mark.parametrize("b_trans", [False, True])
+def test_every_grouped_configuration(b_trans):
+    """Every tiled configuration of a grouped launch (K tails shorter than a
+    K tile, ragged M and N, several sub-tensors per program) matches the
+    oracle and the single launches of the same configuration bitwise."""
+    shapes = [(1, 264, 200), (300, 384, 72), (520, 136, 328),
+              (4352, 256, 136), (130, 1040, 64)]
+    note("every grouped", b_trans, shapes)
+    As = [dev(synth.to_bf16(synth.normal((m, k), 120 + i)))
+          for i, (m, n, k) in enumerate(shapes)]
+    Bs = [dev(synth.to_bf16(synth.normal((n, k) if b_trans else (k, n),
+                                         130 + i)))
+          for i, (m, n, k) in enumerate(shapes)]
+    Cs = [torch.empty((m, n), device=DEV) for m, n, k in shapes]
+    Rs = [reference(A.cpu(), B.cpu(), b_trans) for A, B in zip(As, Bs)]
+    _, _, rows = tg.tile_autotune_grouped(As, Bs, Cs, b_trans=b_trans,
+                                          reps=1)
+    assert len(rows) >= 4
+    for cfg, ms, st in rows:
+        assert st == 0, cfg
+        note("every grouped", b_trans, cfg)
+        for c in Cs:
+            c.fill_(float("nan"))
+        launch = tg.tile_gemm_grouped_prepare(As, Bs, Cs, b_trans=b_trans,
+                                              config=cfg)
+        tg.tile_gemm_grouped(launch)
+        torch.cuda.synchronize()
+        for i, (A, B, C, R) in enumerate(zip(As, Bs, Cs, Rs)):
+            assert rel_err(C.cpu(), R) <= 1e-5, (cfg, i)
+            single = torch.empty_like(C)
+            tg.tile_gemm(A, B, single, cfg["bm"], cfg["bn"], b_trans=b_trans,
+                         config=cfg)
+            torch.cuda.synchronize()
+            assert torch.equal(single, C), (cfg, i)
+
+
 def test_grouped_autotuner_picks_fastest_and_matches_oracle():
     """tile_autotune_grouped times every tiled configuration of the launch
     (B stored N x K, bf16 output here), leaves the workspace prepared with
