@@ -358,6 +358,12 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             int ks = 4;
             while (ks < 16 && progs * ks < (int64_t)std::max(cus, 1))
                 ks *= 2;
+            // no more wavefronts than super-steps of K (eight 16-byte
+            // weight loads per lane each)
+            const int64_t kstep = p.b_dt == TG_BF16 ? 32 : 64;
+            const int64_t super = kstep * 8 / (cfg.bn / 16);
+            const int64_t supers = (p.K + super - 1) / super;
+            while (ks > 1 && ks > supers) ks /= 2;
             cfg.ksplit = ks;
         }
         if (cfg.ksplit != 1 && cfg.ksplit != 2 && cfg.ksplit != 4 &&

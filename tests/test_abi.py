@@ -300,6 +300,14 @@ def test_decode_default_configuration():
         cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
         assert (cfg["kind"], cfg["bn"], cfg["ksplit"]) == \
             (tg.TG_KIND_SKINNY, bn, 4), (wdt, N, K, cfg)
+    # short rows: no more wavefronts than K has super-steps (256 bf16)
+    for K, ks in ((64, 1), (520, 2), (1024, 4)):
+        x = torch.empty((8, K), dtype=torch.bfloat16)
+        W = torch.empty((300, K), dtype=torch.bfloat16)
+        y = torch.empty((8, 300), dtype=torch.bfloat16)
+        cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
+        assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["ksplit"] == ks, \
+            (K, cfg)
 
 
 def test_bench_measures_one_gpu_only():
