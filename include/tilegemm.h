@@ -246,6 +246,25 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
 tg_status tile_gemm_grouped(void *workspace, tg_stream stream);
 
 /*
+ * tile_add -- z = x + y element by element (Sec. 2, the add of the first
+ * listing, measured element-wise in Sec. 5.1), over z's bm x bn partition:
+ * each tile program stores only into the sub-tensors it owns, x and y are
+ * shared reads.
+ * x, y, z: device, one shape (rows x cols, row stride ld), one dtype
+ * (TG_BF16 or TG_F32), not transposed.  Each element is added in binary32
+ * and rounded once to the dtype (round to nearest even), which for bf16 is
+ * the correctly rounded sum.  z->bm = z->bn = 0 selects 1 x 65536
+ * sub-tensors (written back into *z).  opts may be NULL; its checked flag
+ * (default on) runs tile_partition_check's rules with x and y as inputs,
+ * so z may not share bytes with either; opts->write_count counts stores.
+ * Errors: TG_E_ARG / TG_E_SHAPE / TG_E_DTYPE before anything is enqueued;
+ * TG_E_HIP for a failed launch.  z is exclusively borrowed until the
+ * stream passes the launch.
+ */
+tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
+                   const tg_opts *opts, tg_stream stream);
+
+/*
  * tile_error_norm -- binary64 reductions for the relative Frobenius error of
  * a result against a binary64 reference, on the GPU:
  *   out[0] = sum (C[i] - R[i])^2,  out[1] = sum R[i]^2   over i < n

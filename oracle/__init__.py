@@ -17,6 +17,13 @@ What it computes (arxiv 2606.15991):
     every output element.
   * decode_bf16 / decode_e4m3fn -- exact decoding of the two 16/8-bit
     element formats from their published bit layouts.
+  * round_bf16 / add_bf16 / add_f32 -- the element-wise add of Sec. 2 (the
+    first listing; measured element-wise in Sec. 5.1): each output element
+    is the exact sum of the two input elements rounded once to the storage
+    format, to nearest with ties to even.  The binary64 sum of two bf16 or
+    two binary32 values, rounded again to the 8- or 24-bit format, is that
+    correctly rounded sum (53 >= 2p + 2, so the double rounding is
+    innocuous).
   * mlp (submodule) -- binary64 forward/backward of the tile-picker MLP and
     its Adam update.
 """
@@ -147,6 +154,41 @@ def rel_fro(C, R) -> float:
 
 
 PART_OK, PART_ARG, PART_OVERLAP, PART_NOCOVER = 0, 1, 4, 5
+
+
+def round_bf16(v) -> np.ndarray:
+    """binary64 values -> bfloat16 bit patterns (uint16), round to nearest,
+    ties to even, overflow to infinity, NaN -> 0x7FC0 (sign kept).
+
+    bfloat16 keeps 8 significant bits and binary32's exponent range, so the
+    spacing of representable values around |v| in [2^(e-1), 2^e) is
+    2^(e-8), and never below the subnormal spacing 2^-133."""
+    v = np.asarray(v, dtype=np.float64)
+    _, e = np.frexp(v)
+    q = np.ldexp(1.0, np.maximum(e.astype(np.int64) - 8, -133))
+    with np.errstate(over="ignore", invalid="ignore"):
+        r = np.round(v / q) * q                  # np.round: ties to even
+        r = np.where(np.abs(r) >= 2.0 ** 128, np.copysign(np.inf, v), r)
+        r = np.where(np.isinf(v), v, r)
+        bits = (r.astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    nan = np.isnan(v)
+    if nan.any():
+        sign = np.signbit(v).astype(np.uint16) << 15
+        bits = np.where(nan, sign | np.uint16(0x7FC0), bits)
+    return bits.astype(np.uint16)
+
+
+def add_bf16(x_bits, y_bits) -> np.ndarray:
+    """z = x + y for bfloat16 bit patterns: the correctly rounded sum."""
+    with np.errstate(invalid="ignore"):          # inf + (-inf) -> NaN
+        return round_bf16(decode_bf16(x_bits) + decode_bf16(y_bits))
+
+
+def add_f32(x, y) -> np.ndarray:
+    """z = x + y for binary32 arrays: the correctly rounded sum."""
+    with np.errstate(over="ignore", invalid="ignore"):
+        s = np.asarray(x, np.float64) + np.asarray(y, np.float64)
+        return s.astype(np.float32)
 
 
 def partition_paint(M, N, bm, bn, prog_offsets=None, prog_tiles=None):

@@ -102,6 +102,8 @@ def _load():
                               ctypes.c_void_p]
     lib.tile_gemm_workspace_size.argtypes = [P(tg_in), P(tg_in), P(tg_out),
                                              P(tg_opts)]
+    lib.tile_add.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
+                             ctypes.c_void_p]
     lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
     lib.tile_gemm_plan.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                                    P(tg_config), P(i32), ctypes.c_void_p,
@@ -164,7 +166,7 @@ def _load():
         getattr(lib, f).restype = i32
     for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
               "tile_gemm_grouped_prepare", "tile_gemm_grouped",
-              "tile_error_norm"):
+              "tile_add", "tile_error_norm"):
         getattr(lib, f).restype = i32
     return lib
 
@@ -284,6 +286,17 @@ def tile_gemm(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
     _raise(lib.tile_gemm(da, db, dc, o, _stream(stream)))
     tile_gemm.last_partition = (dc.bm, dc.bn)
     return A, B, C
+
+
+def tile_add(x, y, z, bm=0, bn=0, *, checked=True, write_count=None,
+             stream=None):
+    """z = x + y element by element into z's bm x bn partition (bf16 or
+    fp32, one shape and dtype for all three).  Returns z."""
+    dz = make_out(z, bm, bn)
+    o = make_opts(write_count=write_count, checked=checked)
+    _raise(lib.tile_add(make_in(x), make_in(y), dz, o, _stream(stream)))
+    tile_add.last_partition = (dz.bm, dz.bn)
+    return z
 
 
 def tile_gemm_workspace_size(A, B, C, bm=0, bn=0, *, b_trans=False,

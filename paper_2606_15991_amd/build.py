@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libtilegemm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["tilegemm.cpp", "tune.cpp", "gemm_tiled.hip", "gemm_skinny.hip",
-           "gemm_simple.hip", "split_norm.hip", "mlp.hip"]
+           "gemm_simple.hip", "split_norm.hip", "mlp.hip", "elementwise.hip"]
 
 DEVICE_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature",
                 "-Xclang", "-packed-fp32-ops"]

@@ -1,0 +1,160 @@
+// elementwise.hip -- z = x + y over a partitioned output: the tile
+// programs' add (Sec. 2, the first listing; measured element-wise in
+// Sec. 5.1).  z (rows x cols, row stride ldz) is split into bm x bn
+// sub-tensors; the program launched as workgroup p owns sub-tensors
+// p, p + G, ... of the row-major sub-tensor grid and stores only into them;
+// x and y are shared reads.  Every element is added in binary32 and rounded
+// once to the storage type: for bf16 operands (8 significant bits) the
+// binary32 sum (24 bits >= 2 * 8 + 2) rounded to bf16 equals the correctly
+// rounded sum, so the result is the exact sum rounded to nearest even.
+//
+// gfx950: the work is three HBM streams (two reads, one write).  Rows whose
+// byte length and start are 16-byte aligned move in 16-byte chunks, four
+// chunks of x and y in flight per lane before any is added; a row's last
+// partial chunk and unaligned operands go element by element.
+#include "tg_device.hpp"
+#include "tg_internal.hpp"
+
+namespace tg {
+namespace {
+
+constexpr int kAddThreads = 256;
+constexpr int kAddUnroll = 4;
+
+template <int DT>
+struct AddTraits;
+template <>
+struct AddTraits<TG_BF16> {
+    static constexpr int ES = 2;
+    __device__ static float load(const void *p, int64_t i) {
+        const uint32_t b = static_cast<const uint16_t *>(p)[i];
+        return __uint_as_float(b << 16);
+    }
+    __device__ static void store(void *p, int64_t i, float v) {
+        static_cast<uint16_t *>(p)[i] = f32_to_bf16_bits(v);
+    }
+    // eight bf16 sums of a 16-byte chunk pair
+    __device__ static uint4 add16(const uint4 &a, const uint4 &b) {
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+        const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float lo = __uint_as_float(wa[q] << 16) +
+                             __uint_as_float(wb[q] << 16);
+            const float hi = __uint_as_float(wa[q] & 0xffff0000u) +
+                             __uint_as_float(wb[q] & 0xffff0000u);
+            w[q] = (uint32_t)f32_to_bf16_bits(lo) |
+                   ((uint32_t)f32_to_bf16_bits(hi) << 16);
+        }
+        return uint4{w[0], w[1], w[2], w[3]};
+    }
+};
+template <>
+struct AddTraits<TG_F32> {
+    static constexpr int ES = 4;
+    __device__ static float load(const void *p, int64_t i) {
+        return static_cast<const float *>(p)[i];
+    }
+    __device__ static void store(void *p, int64_t i, float v) {
+        static_cast<float *>(p)[i] = v;
+    }
+    __device__ static uint4 add16(const uint4 &a, const uint4 &b) {
+        return uint4{__float_as_uint(__uint_as_float(a.x) + __uint_as_float(b.x)),
+                     __float_as_uint(__uint_as_float(a.y) + __uint_as_float(b.y)),
+                     __float_as_uint(__uint_as_float(a.z) + __uint_as_float(b.z)),
+                     __float_as_uint(__uint_as_float(a.w) + __uint_as_float(b.w))};
+    }
+};
+
+template <int DT, bool VEC>
+__global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
+    using T = AddTraits<DT>;
+    constexpr int EPC = 16 / T::ES;               // elements per chunk
+    const int64_t tiles_n = (g.cols + g.bn - 1) / g.bn;
+    const int64_t tiles = ((g.rows + g.bm - 1) / g.bm) * tiles_n;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t r0 = (t / tiles_n) * g.bm, c0 = (t % tiles_n) * g.bn;
+        const int64_t nr = g.rows - r0 < g.bm ? g.rows - r0 : g.bm;
+        const int64_t nc = g.cols - c0 < g.bn ? g.cols - c0 : g.bn;
+        if constexpr (VEC) {
+            // full chunks of every row of the sub-tensor, then the partial
+            // chunk that ends a row (bn is a multiple of EPC, so only the
+            // last column tile of a row has one)
+            const int64_t cpr = nc / EPC;              // full chunks per row
+            const int64_t total = nr * cpr;
+            const int64_t step = (int64_t)kAddThreads * kAddUnroll;
+            for (int64_t base = threadIdx.x; base < total; base += step) {
+                uint4 a[kAddUnroll], b[kAddUnroll];
+                int64_t off[kAddUnroll][3];
+#pragma unroll
+                for (int u = 0; u < kAddUnroll; ++u) {
+                    const int64_t q = base + (int64_t)u * kAddThreads;
+                    if (q < total) {
+                        const int64_t r = r0 + q / cpr;
+                        const int64_t c = c0 + (q % cpr) * EPC;
+                        off[u][0] = (r * g.ldx + c) * T::ES;
+                        off[u][1] = (r * g.ldy + c) * T::ES;
+                        off[u][2] = (r * g.ldz + c) * T::ES;
+                        a[u] = ld16(static_cast<const char *>(g.x) + off[u][0]);
+                        b[u] = ld16(static_cast<const char *>(g.y) + off[u][1]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kAddUnroll; ++u) {
+                    const int64_t q = base + (int64_t)u * kAddThreads;
+                    if (q < total)
+                        st16(static_cast<char *>(g.z) + off[u][2],
+                             T::add16(a[u], b[u]));
+                }
+            }
+            const int64_t rest = nc - cpr * EPC;
+            for (int64_t q = threadIdx.x; q < nr * rest; q += kAddThreads) {
+                const int64_t r = r0 + q / rest;
+                const int64_t c = c0 + cpr * EPC + q % rest;
+                T::store(g.z, r * g.ldz + c,
+                         T::load(g.x, r * g.ldx + c) +
+                             T::load(g.y, r * g.ldy + c));
+            }
+        } else {
+            for (int64_t q = threadIdx.x; q < nr * nc; q += kAddThreads) {
+                const int64_t r = r0 + q / nc, c = c0 + q % nc;
+                T::store(g.z, r * g.ldz + c,
+                         T::load(g.x, r * g.ldx + c) +
+                             T::load(g.y, r * g.ldy + c));
+            }
+        }
+        if (g.wcount) {
+            // instrumented launches: one count per stored element
+            for (int64_t q = threadIdx.x; q < nr * nc; q += kAddThreads)
+                atomicAdd(&g.wcount[(r0 + q / nc) * g.cols + c0 + q % nc], 1);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_add(const AddArgs &a, bool vec, int programs,
+                      hipStream_t st) {
+    dim3 grid(programs), block(kAddThreads);
+    if (a.dtype == TG_BF16) {
+        if (vec)
+            hipLaunchKernelGGL((add_kernel<TG_BF16, true>), grid, block, 0,
+                               st, a);
+        else
+            hipLaunchKernelGGL((add_kernel<TG_BF16, false>), grid, block, 0,
+                               st, a);
+    } else if (a.dtype == TG_F32) {
+        if (vec)
+            hipLaunchKernelGGL((add_kernel<TG_F32, true>), grid, block, 0, st,
+                               a);
+        else
+            hipLaunchKernelGGL((add_kernel<TG_F32, false>), grid, block, 0,
+                               st, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tg

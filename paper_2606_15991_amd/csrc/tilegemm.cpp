@@ -940,6 +940,62 @@ tg_status tile_gemm_grouped(void *ws, tg_stream stream) {
     return e == hipSuccess ? TG_OK : hip_fail(e, "grouped kernel launch");
 }
 
+tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
+                   const tg_opts *opts, tg_stream stream) {
+    g_err.clear();
+    tg_status st;
+    if ((st = check_in(x, "x")) != TG_OK) return st;
+    if ((st = check_in(y, "y")) != TG_OK) return st;
+    if ((st = check_out(z, false)) != TG_OK) return st;
+    if (x->trans || y->trans)
+        return fail(TG_E_SHAPE, "element-wise operands are not transposed");
+    if (x->dtype != z->dtype || y->dtype != z->dtype)
+        return fail(TG_E_DTYPE, "x, y and z must share one dtype");
+    if (x->rows != z->rows || x->cols != z->cols || y->rows != z->rows ||
+        y->cols != z->cols)
+        return fail(TG_E_SHAPE, "x, y and z must have one shape");
+    const int es = esize(z->dtype), epc = 16 / es;
+    if (z->bm == 0 && z->bn == 0) {
+        // one row segment of up to 65536 elements per sub-tensor
+        z->bm = 1;
+        const int64_t bn = std::min<int64_t>(std::max<int64_t>(z->cols, 1),
+                                             65536);
+        z->bn = (int32_t)((bn + epc - 1) / epc * epc);
+    }
+    const bool checked = !opts || opts->checked;
+    if (checked) {
+        const tg_in ins[2] = {*x, *y};
+        if ((st = tile_partition_check(ins, 2, z, 0, nullptr, nullptr)) !=
+            TG_OK)
+            return st;
+    } else if (z->bm <= 0 || z->bn <= 0) {
+        return fail(TG_E_ARG, "z: partition %d x %d must be positive", z->bm,
+                    z->bn);
+    }
+    if (z->rows == 0 || z->cols == 0) return TG_OK;
+    auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    const bool vec = al(x->data) && al(y->data) && al(z->data) &&
+                     (x->ld * es) % 16 == 0 && (y->ld * es) % 16 == 0 &&
+                     (z->ld * es) % 16 == 0 && z->bn % epc == 0;
+    AddArgs a;
+    a.x = x->data; a.y = y->data; a.z = z->data;
+    a.wcount = opts ? opts->write_count : nullptr;
+    a.ldx = x->rows > 1 ? x->ld : x->cols;
+    a.ldy = y->rows > 1 ? y->ld : y->cols;
+    a.ldz = z->rows > 1 ? z->ld : z->cols;
+    a.rows = z->rows; a.cols = z->cols;
+    a.bm = z->bm; a.bn = z->bn;
+    a.dtype = z->dtype;
+    const int64_t tiles = ((z->rows + z->bm - 1) / z->bm) *
+                          ((z->cols + z->bn - 1) / z->bn);
+    const int cus = device_cus();
+    const int programs =
+        (int)std::min<int64_t>(tiles, (int64_t)std::max(cus, 1) * 8);
+    hipError_t e = launch_add(a, vec, programs,
+                              static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TG_OK : hip_fail(e, "element-wise launch");
+}
+
 tg_status tile_error_norm(const void *C, int32_t c_dtype, const double *R,
                           int64_t n, double *out, tg_stream stream) {
     g_err.clear();

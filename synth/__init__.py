@@ -115,3 +115,10 @@ def mlp_init(n_in: int, hidden: int, depth: int, seed: int) -> torch.Tensor:
                       * 2 - 1).mul(lim).reshape(-1))
         parts.append(torch.zeros(o, dtype=torch.float64))
     return torch.cat(parts).to(torch.float32)
+
+
+def random_codes16(shape, seed: int) -> torch.Tensor:
+    """Uniformly random 16-bit patterns (int16): as bfloat16 they cover every
+    exponent, both zeros, subnormals, infinities and NaNs."""
+    return torch.randint(-32768, 32768, shape, generator=gen(seed),
+                         dtype=torch.int32).to(torch.int16)

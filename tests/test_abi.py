@@ -239,6 +239,35 @@ def test_tile_gemm_rejects_before_enqueue():
     assert "tiled kernel" in tg.last_error()
 
 
+def _add_err(x, y, z, bm=0, bn=0, checked=True):
+    dz = tg.make_out(z, bm, bn)
+    st = tg.lib.tile_add(tg.make_in(x), tg.make_in(y), dz,
+                         tg.make_opts(checked=checked), None)
+    return st, (dz.bm, dz.bn)
+
+
+def test_tile_add_rejects_before_enqueue():
+    bf = torch.bfloat16
+    x, y, z = (torch.empty((64, 48), dtype=bf) for _ in range(3))
+    assert _add_err(x, y.float(), z)[0] == tg.TG_E_DTYPE
+    assert _add_err(x, y, z.float())[0] == tg.TG_E_DTYPE
+    assert _add_err(x, torch.empty((64, 47), dtype=bf), z)[0] == \
+        tg.TG_E_SHAPE
+    assert _add_err(x, y, x)[0] == tg.TG_E_ALIAS
+    buf = torch.empty((64, 96), dtype=bf)
+    assert _add_err(buf[:, :48], y, buf[:, 40:88])[0] == tg.TG_E_ALIAS
+    assert _add_err(x, y, z, bm=-1, bn=8)[0] == tg.TG_E_ARG
+    e = torch.empty((64, 48), dtype=torch.float8_e4m3fn)
+    assert _add_err(e, e.clone(), e.clone())[0] != tg.TG_OK
+    # empty shapes succeed without touching the device; the default
+    # partition is one row segment of whole 16-byte chunks
+    st, part = _add_err(*(torch.empty((0, 5), dtype=bf) for _ in range(3)))
+    assert st == tg.TG_OK and part == (1, 8)
+    st, part = _add_err(*(torch.empty((3, 0), dtype=torch.float32)
+                          for _ in range(3)))
+    assert st == tg.TG_OK and part == (1, 4)
+
+
 def test_status_strings():
     assert tg.status_str(tg.TG_E_OVERLAP) == "TG_E_OVERLAP"
     assert tg.status_str(99) == "unknown status"
