@@ -17,6 +17,7 @@
 // operands go element by element.
 #include "tg_device.hpp"
 #include "tg_internal.hpp"
+#include "tg_elementwise.hpp"
 
 namespace tg {
 namespace {

@@ -1,0 +1,26 @@
+// tg_elementwise.hpp -- host-side launch interface of the element-wise
+// kernels (add, RMS normalisation) shared by the entry points and the
+// kernel sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tilegemm.h"
+
+namespace tg {
+
+// Element-wise z = x + y over z's bm x bn partition.
+struct AddArgs {
+    const void *x;
+    const void *y;
+    void *z;
+    int32_t *wcount;
+    int64_t ldx, ldy, ldz;
+    int64_t rows, cols;
+    int64_t bm, bn;
+    int32_t dtype;       // TG_BF16 or TG_F32, all three operands
+};
+hipError_t launch_add(const AddArgs &a, bool vec, int programs,
+                      hipStream_t st);
+
+}  // namespace tg

@@ -146,18 +146,4 @@ hipError_t launch_split_rows(const float *src, int64_t ld, int32_t rows,
 hipError_t launch_error_norm(const void *c, int c_bf16, const double *r,
                              int64_t n, double *out, hipStream_t st);
 
-// Element-wise z = x + y over z's bm x bn partition.
-struct AddArgs {
-    const void *x;
-    const void *y;
-    void *z;
-    int32_t *wcount;
-    int64_t ldx, ldy, ldz;
-    int64_t rows, cols;
-    int64_t bm, bn;
-    int32_t dtype;       // TG_BF16 or TG_F32, all three operands
-};
-hipError_t launch_add(const AddArgs &a, bool vec, int programs,
-                      hipStream_t st);
-
 }  // namespace tg

@@ -15,6 +15,7 @@
 
 #include "host_internal.hpp"
 #include "tg_internal.hpp"
+#include "tg_elementwise.hpp"
 
 using namespace tg;
 
