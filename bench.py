@@ -374,6 +374,38 @@ def bench_add(args, tg, n=16384):
     return out
 
 
+def bench_decode_layer(args, tg, d=5120, layers=16):
+    """The decode layer rms_norm -> matvec (d x d bf16 weights stored N x K)
+    -> residual add at M = 1, over `layers` layers with weights of their own
+    (16 x 52 MB, more than the Infinity Cache holds), launched eagerly and
+    as one captured graph; time per layer and weight-stream GB/s."""
+    xs = synth.to_bf16(synth.normal((1, d), 71)).cuda()
+    nw = (1.0 + synth.normal((d,), 72, std=0.1)).to(torch.bfloat16).cuda()
+    Ws = [synth.to_bf16(synth.normal((d, d), 100 + i, std=0.02)).cuda()
+          for i in range(layers)]
+    bufs = [torch.empty((1, d), dtype=torch.bfloat16, device="cuda")
+            for _ in range(3 * layers)]
+
+    def run(stream=None):
+        h = xs
+        for i in range(layers):
+            norm, q, res = bufs[3 * i:3 * i + 3]
+            tg.tile_rms_norm(h, nw, norm, 1e-6, checked=False, stream=stream)
+            tg.tile_gemm(norm, Ws[i], q, b_trans=True, checked=False,
+                         stream=stream)
+            tg.tile_add(h, q, res, checked=False, stream=stream)
+            h = res
+    ms_eager = timed(run, 20, 5)
+    ms_graph = graph_ms([lambda st: run(stream=st)], reps=20)
+    wbytes = 2.0 * d * d
+    out = {"d": d, "layers": layers,
+           "us_per_layer_eager": ms_eager * 1e3 / layers,
+           "us_per_layer_graph": ms_graph * 1e3 / layers,
+           "weight_gbs_graph": wbytes * layers / (ms_graph * 1e-3) / 1e9}
+    log("decode layer", out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +420,8 @@ def main():
                     help="only the decode-shaped products (one JSON line)")
     ap.add_argument("--add", action="store_true",
                     help="only the element-wise add (one JSON line)")
+    ap.add_argument("--layer", action="store_true",
+                    help="only the decode layer rms_norm -> matvec -> add")
     ap.add_argument("--library-reference", action="store_true",
                     help="only time the vendor bf16 GEMM beside the "
                          "headline launch")
@@ -416,6 +450,10 @@ def main():
         print(json.dumps({"elementwise_add": bench_add(args, tg)}),
               flush=True)
         return
+    if args.layer:
+        print(json.dumps({"decode_layer": bench_decode_layer(args, tg)}),
+              flush=True)
+        return
 
     res = bench_bf16_main(args, tg)
     extra = {"ms_unchecked_launch": res["ms_unchecked"],
@@ -427,6 +465,7 @@ def main():
         extra["grouped"] = bench_grouped(args, tg)
         extra["bf16_8192_b_row_major"] = bench_bf16_kn(args, tg)
         extra["elementwise_add"] = bench_add(args, tg)
+        extra["decode_layer"] = bench_decode_layer(args, tg)
     if args.picker:
         from paper_2606_15991_amd import picker
         import io

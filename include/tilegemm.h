@@ -265,6 +265,25 @@ tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
                    const tg_opts *opts, tg_stream stream);
 
 /*
+ * tile_rms_norm -- y = x * w / sqrt(mean(x^2) + eps) row by row: the RMS
+ * normalisation that opens the decode layer of Sec. 3.2's graph-scope
+ * listing (partitioned [1, d]: each program owns whole rows).
+ * x, y: device, rows x cols (row stride ld); w: device, 1 x cols; one dtype
+ * (TG_BF16 or TG_F32), not transposed.  Sums of squares in binary32 in a
+ * fixed order (deterministic); each output x * scale * w is computed in
+ * binary32 and rounded once to the dtype.  eps: finite, >= 0.
+ * y->bm x y->bn is the partition; bn must equal cols; 0 x 0 selects
+ * 1 x cols (written back into *y).  opts may be NULL; its checked flag
+ * (default on) applies tile_partition_check's rules with x and w as inputs;
+ * opts->write_count counts stores.
+ * Errors: TG_E_ARG / TG_E_SHAPE / TG_E_DTYPE before anything is enqueued;
+ * TG_E_HIP for a failed launch.  y is exclusively borrowed until the stream
+ * passes the launch.
+ */
+tg_status tile_rms_norm(const tg_in *x, const tg_in *w, float eps, tg_out *y,
+                        const tg_opts *opts, tg_stream stream);
+
+/*
  * tile_error_norm -- binary64 reductions for the relative Frobenius error of
  * a result against a binary64 reference, on the GPU:
  *   out[0] = sum (C[i] - R[i])^2,  out[1] = sum R[i]^2   over i < n

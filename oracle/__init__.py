@@ -24,6 +24,10 @@ What it computes (arxiv 2606.15991):
     two binary32 values, rounded again to the 8- or 24-bit format, is that
     correctly rounded sum (53 >= 2p + 2, so the double rounding is
     innocuous).
+  * rms_norm -- the RMS normalisation of the decode layer in Sec. 3.2's
+    graph-scope listing, y = x * w / sqrt(mean(x^2) + eps) per row, in
+    binary64 (the usual RMSNorm definition; the paper names the operation
+    and its eps without writing the formula out).
   * mlp (submodule) -- binary64 forward/backward of the tile-picker MLP and
     its Adam update.
 """
@@ -189,6 +193,14 @@ def add_f32(x, y) -> np.ndarray:
     with np.errstate(over="ignore", invalid="ignore"):
         s = np.asarray(x, np.float64) + np.asarray(y, np.float64)
         return s.astype(np.float32)
+
+
+def rms_norm(x, w, eps: float) -> np.ndarray:
+    """binary64 y[r, j] = x[r, j] w[j] / sqrt(mean_j(x[r, j]^2) + eps)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    w = np.asarray(w, dtype=np.float64).reshape(-1)
+    ms = np.mean(x * x, axis=1, keepdims=True)
+    return x * w / np.sqrt(ms + float(eps))
 
 
 def partition_paint(M, N, bm, bn, prog_offsets=None, prog_tiles=None):

@@ -104,6 +104,8 @@ def _load():
                                              P(tg_opts)]
     lib.tile_add.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                              ctypes.c_void_p]
+    lib.tile_rms_norm.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
+                                  P(tg_out), P(tg_opts), ctypes.c_void_p]
     lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
     lib.tile_gemm_plan.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                                    P(tg_config), P(i32), ctypes.c_void_p,
@@ -166,7 +168,7 @@ def _load():
         getattr(lib, f).restype = i32
     for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
               "tile_gemm_grouped_prepare", "tile_gemm_grouped",
-              "tile_add", "tile_error_norm"):
+              "tile_add", "tile_rms_norm", "tile_error_norm"):
         getattr(lib, f).restype = i32
     return lib
 
@@ -297,6 +299,20 @@ def tile_add(x, y, z, bm=0, bn=0, *, checked=True, write_count=None,
     _raise(lib.tile_add(make_in(x), make_in(y), dz, o, _stream(stream)))
     tile_add.last_partition = (dz.bm, dz.bn)
     return z
+
+
+def tile_rms_norm(x, w, y, eps=1e-6, bm=0, *, checked=True,
+                  write_count=None, stream=None):
+    """y = x * w / sqrt(mean(x^2) + eps) per row (x, y rows x d; w of d
+    elements, 1-D or 1 x d), into y's bm x d partition.  Returns y."""
+    if w.dim() == 1:
+        w = w.view(1, -1)
+    dy = make_out(y, bm, y.shape[1] if bm else 0)
+    o = make_opts(write_count=write_count, checked=checked)
+    _raise(lib.tile_rms_norm(make_in(x), make_in(w), float(eps), dy, o,
+                             _stream(stream)))
+    tile_rms_norm.last_partition = (dy.bm, dy.bn)
+    return y
 
 
 def tile_gemm_workspace_size(A, B, C, bm=0, bn=0, *, b_trans=False,

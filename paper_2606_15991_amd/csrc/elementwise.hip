@@ -66,6 +66,35 @@ struct AddTraits<TG_BF16> {
         }
         return uint4{w[0], w[1], w[2], w[3]};
     }
+    // sum of the squares of the eight values of a chunk
+    __device__ static float sumsq16(const uint4 &a) {
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float lo = __uint_as_float(wa[q] << 16);
+            const float hi = __uint_as_float(wa[q] & 0xffff0000u);
+            s += lo * lo;
+            s += hi * hi;
+        }
+        return s;
+    }
+    // x * scale * w for the eight values of a chunk, rounded to bf16
+    __device__ static uint4 scale16(const uint4 &a, const uint4 &b, float sc) {
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+        const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float lo = __uint_as_float(wa[q] << 16) * sc *
+                             __uint_as_float(wb[q] << 16);
+            const float hi = __uint_as_float(wa[q] & 0xffff0000u) * sc *
+                             __uint_as_float(wb[q] & 0xffff0000u);
+            w[q] = (uint32_t)f32_to_bf16_bits(lo) |
+                   ((uint32_t)f32_to_bf16_bits(hi) << 16);
+        }
+        return uint4{w[0], w[1], w[2], w[3]};
+    }
 };
 template <>
 struct AddTraits<TG_F32> {
@@ -81,6 +110,21 @@ struct AddTraits<TG_F32> {
                      __float_as_uint(__uint_as_float(a.y) + __uint_as_float(b.y)),
                      __float_as_uint(__uint_as_float(a.z) + __uint_as_float(b.z)),
                      __float_as_uint(__uint_as_float(a.w) + __uint_as_float(b.w))};
+    }
+    __device__ static float sumsq16(const uint4 &a) {
+        const float v[4] = {__uint_as_float(a.x), __uint_as_float(a.y),
+                            __uint_as_float(a.z), __uint_as_float(a.w)};
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s += v[q] * v[q];
+        return s;
+    }
+    __device__ static uint4 scale16(const uint4 &a, const uint4 &b, float sc) {
+        return uint4{
+            __float_as_uint(__uint_as_float(a.x) * sc * __uint_as_float(b.x)),
+            __float_as_uint(__uint_as_float(a.y) * sc * __uint_as_float(b.y)),
+            __float_as_uint(__uint_as_float(a.z) * sc * __uint_as_float(b.z)),
+            __float_as_uint(__uint_as_float(a.w) * sc * __uint_as_float(b.w))};
     }
 };
 
@@ -161,7 +205,116 @@ __global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
     }
 }
 
+// RMS normalisation (the first step of the decode layer of Sec. 3.2's
+// graph-scope listing): y[r, :] = x[r, :] * w / sqrt(mean(x[r, :]^2) + eps).
+// y is split into bm x cols sub-tensors (whole rows: a row's scale needs
+// every element of the row); program p owns sub-tensors p, p + G, ...  The
+// sum of squares is accumulated in binary32 per lane, then over each
+// wavefront and the four wavefronts in a fixed order (deterministic); each
+// output is x * scale * w in binary32 rounded once to the storage type.
+constexpr int kNormThreads = 256;
+
+// With VEC (x, w, y 16-byte aligned, rows a whole number of 16-byte
+// chunks apart) each lane moves 16-byte chunks, kNormUnroll of them in
+// flight before any is used: a decode row (one program, 5120 bf16) is then
+// two or three memory round trips instead of one per element.  The row is
+// read twice (the second pass mostly from cache).
+constexpr int kNormUnroll = 4;
+
+template <int DT, bool VEC>
+__global__ __launch_bounds__(kNormThreads) void rms_norm_kernel(NormArgs g) {
+    using T = AddTraits<DT>;
+    constexpr int EPC = 16 / T::ES;
+    constexpr int U = kNormUnroll;
+    __shared__ float red[kNormThreads / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t tiles = (g.rows + g.bm - 1) / g.bm;
+    const int64_t nch = VEC ? g.cols / EPC : 0;      // whole chunks per row
+    const int64_t c_rest = nch * EPC;                // first scalar column
+    const char *W = static_cast<const char *>(g.w);
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int64_t r0 = t * g.bm;
+        const int64_t nr = g.rows - r0 < g.bm ? g.rows - r0 : g.bm;
+        for (int64_t i = 0; i < nr; ++i) {
+            const int64_t r = r0 + i;
+            const char *X = static_cast<const char *>(g.x) + r * g.ldx * T::ES;
+            char *Y = static_cast<char *>(g.y) + r * g.ldy * T::ES;
+            float ss = 0.f;
+            for (int64_t base = threadIdx.x; base < nch;
+                 base += kNormThreads * U) {
+                uint4 a[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t q = base + u * kNormThreads;
+                    a[u] = q < nch ? ld16(X + q * 16) : uint4{0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) ss += T::sumsq16(a[u]);
+            }
+            for (int64_t c = c_rest + threadIdx.x; c < g.cols;
+                 c += kNormThreads) {
+                const float v = T::load(X, c);
+                ss += v * v;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+            if (lane == 0) red[wave] = ss;
+            __syncthreads();
+            float tot = red[0];
+#pragma unroll
+            for (int q = 1; q < kNormThreads / 64; ++q) tot += red[q];
+            __syncthreads();                  // red is rewritten next row
+            const float scale = 1.0f / sqrtf(tot / (float)g.cols + g.eps);
+            for (int64_t base = threadIdx.x; base < nch;
+                 base += kNormThreads * U) {
+                uint4 a[U], b[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t q = base + u * kNormThreads;
+                    if (q < nch) {
+                        a[u] = ld16(X + q * 16);
+                        b[u] = ld16(W + q * 16);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t q = base + u * kNormThreads;
+                    if (q < nch) st16(Y + q * 16, T::scale16(a[u], b[u], scale));
+                }
+            }
+            for (int64_t c = c_rest + threadIdx.x; c < g.cols;
+                 c += kNormThreads)
+                T::store(Y, c, T::load(X, c) * scale * T::load(W, c));
+            if (g.wcount) {
+                for (int64_t c = threadIdx.x; c < g.cols; c += kNormThreads)
+                    atomicAdd(&g.wcount[r * g.cols + c], 1);
+            }
+        }
+    }
+}
+
 }  // namespace
+
+template <int DT>
+void launch_norm_dt(const NormArgs &a, bool vec, dim3 grid, hipStream_t st) {
+    if (vec)
+        hipLaunchKernelGGL((rms_norm_kernel<DT, true>), grid,
+                           dim3(kNormThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL((rms_norm_kernel<DT, false>), grid,
+                           dim3(kNormThreads), 0, st, a);
+}
+
+hipError_t launch_rms_norm(const NormArgs &a, bool vec, int programs,
+                           hipStream_t st) {
+    if (a.dtype == TG_BF16)
+        launch_norm_dt<TG_BF16>(a, vec, dim3(programs), st);
+    else if (a.dtype == TG_F32)
+        launch_norm_dt<TG_F32>(a, vec, dim3(programs), st);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_add(const AddArgs &a, bool vec, int programs,
                       hipStream_t st) {

@@ -23,4 +23,19 @@ struct AddArgs {
 hipError_t launch_add(const AddArgs &a, bool vec, int programs,
                       hipStream_t st);
 
+// y = x * w / sqrt(mean(x^2) + eps) per row, over y's bm x cols partition.
+struct NormArgs {
+    const void *x;
+    const void *w;      // one row of cols weights
+    void *y;
+    int32_t *wcount;
+    int64_t ldx, ldy;
+    int64_t rows, cols;
+    int64_t bm;
+    float eps;
+    int32_t dtype;      // TG_BF16 or TG_F32: x, w and y
+};
+hipError_t launch_rms_norm(const NormArgs &a, bool vec, int programs,
+                           hipStream_t st);
+
 }  // namespace tg

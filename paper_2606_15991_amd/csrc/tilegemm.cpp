@@ -999,6 +999,62 @@ tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
     return e == hipSuccess ? TG_OK : hip_fail(e, "element-wise launch");
 }
 
+tg_status tile_rms_norm(const tg_in *x, const tg_in *w, float eps,
+                        tg_out *y, const tg_opts *opts, tg_stream stream) {
+    g_err.clear();
+    tg_status st;
+    if ((st = check_in(x, "x")) != TG_OK) return st;
+    if ((st = check_in(w, "w")) != TG_OK) return st;
+    if ((st = check_out(y, false)) != TG_OK) return st;
+    if (x->trans || w->trans)
+        return fail(TG_E_SHAPE, "normalisation operands are not transposed");
+    if (x->dtype != y->dtype || w->dtype != y->dtype)
+        return fail(TG_E_DTYPE, "x, w and y must share one dtype");
+    if (x->rows != y->rows || x->cols != y->cols)
+        return fail(TG_E_SHAPE, "x and y must have one shape");
+    if (w->rows != 1 || w->cols != y->cols)
+        return fail(TG_E_SHAPE, "w must be 1 x %lld", (long long)y->cols);
+    if (!(eps >= 0.0f) || !std::isfinite(eps))
+        return fail(TG_E_ARG, "eps must be finite and >= 0");
+    if (y->bm == 0 && y->bn == 0) {
+        y->bm = 1;
+        y->bn = (int32_t)std::max<int64_t>(y->cols, 1);
+    }
+    if (y->cols > 0 && y->bn != y->cols)
+        return fail(TG_E_ARG, "y: sub-tensors must span whole rows (bn %d, "
+                    "cols %lld)", y->bn, (long long)y->cols);
+    const bool checked = !opts || opts->checked;
+    if (checked) {
+        const tg_in ins[2] = {*x, *w};
+        if ((st = tile_partition_check(ins, 2, y, 0, nullptr, nullptr)) !=
+            TG_OK)
+            return st;
+    } else if (y->bm <= 0 || y->bn <= 0) {
+        return fail(TG_E_ARG, "y: partition %d x %d must be positive", y->bm,
+                    y->bn);
+    }
+    if (y->rows == 0 || y->cols == 0) return TG_OK;
+    NormArgs a;
+    a.x = x->data; a.w = w->data; a.y = y->data;
+    a.wcount = opts ? opts->write_count : nullptr;
+    a.ldx = x->rows > 1 ? x->ld : x->cols;
+    a.ldy = y->rows > 1 ? y->ld : y->cols;
+    a.rows = y->rows; a.cols = y->cols;
+    a.bm = y->bm;
+    a.eps = eps;
+    a.dtype = y->dtype;
+    const int64_t tiles = (y->rows + y->bm - 1) / y->bm;
+    const int programs = (int)std::min<int64_t>(
+        tiles, (int64_t)std::max(device_cus(), 1) * 8);
+    const int es = esize(y->dtype);
+    auto al = [](const void *p) { return ((uintptr_t)p & 15) == 0; };
+    const bool vec = al(x->data) && al(w->data) && al(y->data) &&
+                     (a.ldx * es) % 16 == 0 && (a.ldy * es) % 16 == 0;
+    hipError_t e = launch_rms_norm(a, vec, programs,
+                                   static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TG_OK : hip_fail(e, "normalisation launch");
+}
+
 tg_status tile_error_norm(const void *C, int32_t c_dtype, const double *R,
                           int64_t n, double *out, tg_stream stream) {
     g_err.clear();

@@ -268,6 +268,24 @@ def test_tile_add_rejects_before_enqueue():
     assert st == tg.TG_OK and part == (1, 4)
 
 
+def test_tile_rms_norm_rejects_before_enqueue():
+    bf = torch.bfloat16
+    x, y = torch.empty((4, 64), dtype=bf), torch.empty((4, 64), dtype=bf)
+    w = torch.empty((1, 64), dtype=bf)
+
+    def err(x, w, y, eps=1e-6, bm=0, bn=0):
+        return tg.lib.tile_rms_norm(tg.make_in(x), tg.make_in(w), eps,
+                                    tg.make_out(y, bm, bn), None, None)
+    assert err(x, w[:, :32], y) == tg.TG_E_SHAPE
+    assert err(x, w, y, bm=1, bn=32) == tg.TG_E_ARG     # not whole rows
+    assert err(x, w, y, eps=-1.0) == tg.TG_E_ARG
+    assert err(x, w, y, eps=float("nan")) == tg.TG_E_ARG
+    assert err(x, w.float(), y) == tg.TG_E_DTYPE
+    assert err(x, w, x) == tg.TG_E_ALIAS
+    e = torch.empty((0, 64), dtype=bf)
+    assert err(e, w, torch.empty((0, 64), dtype=bf)) == tg.TG_OK
+
+
 def test_status_strings():
     assert tg.status_str(tg.TG_E_OVERLAP) == "TG_E_OVERLAP"
     assert tg.status_str(99) == "unknown status"

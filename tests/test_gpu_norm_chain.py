@@ -1,0 +1,142 @@
+"""RMS normalisation and the decode layer of Sec. 3.2's graph-scope listing
+(rms_norm -> matvec -> residual add) on the GPU, against the oracle.
+
+Tolerances:
+  * rms_norm, binary32 output: relative 1e-5 per element (binary32 sum of
+    squares over <= 5120 elements in a fixed tree, then about six roundings:
+    about 2.5e-6 at most);
+  * rms_norm, bf16 output: relative 2^-8 + 1e-5 per element (one bf16
+    rounding of the binary32 value: bf16 keeps 8 significant bits, so its
+    unit roundoff is 2^-8);
+  * the layer (bf16 buffers): relative Frobenius 4e-3 against the oracle's
+    chain, which rounds each intermediate buffer to bf16 as the layer
+    stores it (bf16 unit roundoff 2^-8).
+The graph replays are compared bit for bit with the eager layer (every
+kernel is deterministic)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import exact64, note, rel_err
+
+pytestmark = pytest.mark.gpu
+
+tg = pytest.importorskip("paper_2606_15991_amd")
+DEV = "cuda:0"
+
+
+def norm_inputs(rows, d, dt, seed):
+    x = synth.normal((rows, d), seed, std=2.0).to(dt)
+    w = (1.0 + synth.normal((d,), seed + 1, std=0.1)).to(dt)
+    return x, w
+
+
+def check_norm(y, x, w, eps, dt):
+    want = oracle.rms_norm(exact64(x), exact64(w), eps)
+    got = exact64(y)
+    tol = 1e-5 if dt == torch.float32 else 2.0 ** -8 + 1e-5
+    bad = np.abs(got - want) > tol * np.abs(want) + 1e-30
+    assert not bad.any(), f"{bad.sum()} elements, first {np.argwhere(bad)[:3]}"
+
+
+@pytest.mark.parametrize("rows,d", [(1, 5120), (3, 1000), (16, 4096), (7, 33),
+                                    (1, 1), (2, 70000)])
+@pytest.mark.parametrize("dt", [torch.bfloat16, torch.float32])
+def test_rms_norm_matches_oracle(rows, d, dt):
+    note("rms_norm", rows, d, dt)
+    x, w = norm_inputs(rows, d, dt, 7)
+    y = torch.full((rows, d), 5.0, dtype=dt, device=DEV)
+    tg.tile_rms_norm(x.to(DEV), w.to(DEV), y, 1e-6)
+    torch.cuda.synchronize()
+    check_norm(y, x, w, 1e-6, dt)
+
+
+def test_rms_norm_partition_and_write_count():
+    note("rms_norm partition 3 rows")
+    x, w = norm_inputs(10, 300, torch.bfloat16, 9)
+    y = torch.empty((10, 300), dtype=torch.bfloat16, device=DEV)
+    wc = torch.zeros((10, 300), dtype=torch.int32, device=DEV)
+    tg.tile_rms_norm(x.to(DEV), w.to(DEV), y, 0.5, bm=3, write_count=wc)
+    torch.cuda.synchronize()
+    assert tg.tile_rms_norm.last_partition == (3, 300)
+    assert int(wc.min()) == 1 and int(wc.max()) == 1
+    check_norm(y, x, w, 0.5, torch.bfloat16)
+
+
+def test_rms_norm_rejects_bad_arguments():
+    note("rms_norm argument errors")
+    x = torch.ones((4, 64), dtype=torch.bfloat16, device=DEV)
+    w = torch.ones((64,), dtype=torch.bfloat16, device=DEV)
+    y = torch.empty_like(x)
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm(x, w[:32], y)
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm(x, w, y, eps=-1.0)
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm(x, w, x)                      # y is an input
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm(x, w.float(), y)
+    dy = tg.make_out(y, 1, 32)                         # not whole rows
+    assert tg.lib.tile_rms_norm(tg.make_in(x), tg.make_in(w.view(1, -1)),
+                                1e-6, dy, None, None) == tg.TG_E_ARG
+
+
+class Layer:
+    """One decode layer: norm = rms_norm(input), q = norm . Wq^T,
+    residual = input + q, all bf16 buffers allocated up front."""
+
+    def __init__(self, d, seed):
+        self.x = synth.to_bf16(synth.normal((1, d), seed)).to(DEV)
+        self.nw = (1.0 + synth.normal((d,), seed + 1, std=0.1)).to(
+            torch.bfloat16).to(DEV)
+        self.W = synth.to_bf16(synth.normal((d, d), seed + 2, std=0.02)).to(
+            DEV)
+        self.norm = torch.empty((1, d), dtype=torch.bfloat16, device=DEV)
+        self.q = torch.empty_like(self.norm)
+        self.res = torch.empty_like(self.norm)
+        self.eps = 1e-6
+
+    def run(self, stream=None):
+        tg.tile_rms_norm(self.x, self.nw, self.norm, self.eps, stream=stream)
+        tg.tile_gemm(self.norm, self.W, self.q, b_trans=True, stream=stream)
+        tg.tile_add(self.x, self.q, self.res, stream=stream)
+
+    def oracle(self):
+        """The chain in binary64 with each stored buffer rounded to bf16."""
+        xb = self.x.cpu().view(torch.int16).numpy().view(np.uint16)
+        n = oracle.round_bf16(oracle.rms_norm(oracle.decode_bf16(xb),
+                                              exact64(self.nw), self.eps))
+        q = oracle.round_bf16(oracle.gemm(oracle.decode_bf16(n),
+                                          exact64(self.W), b_nk=True))
+        return oracle.decode_bf16(oracle.add_bf16(xb, q))
+
+
+@pytest.mark.parametrize("d", [5120, 1000])
+def test_decode_layer_eager_and_graph_replays(d):
+    note("decode layer", d)
+    L = Layer(d, 21)
+    L.run()
+    torch.cuda.synchronize()
+    eager = L.res.clone()
+    assert rel_err(eager, L.oracle()) < 4e-3
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        L.run(stream=s)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            L.run(stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        L.res.fill_(0.0)
+        L.q.fill_(0.0)
+        L.norm.fill_(0.0)
+        (L.W[:64].float() * 3.0).sum()                # eager work between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(L.res.view(torch.int16), eager.view(torch.int16)), \
+            f"replay {rep} differs from the eager layer"

@@ -1,0 +1,58 @@
+"""Pins of the oracle's RMS normalisation (CPU): closed forms and
+invariants that fix the definition y = x w / sqrt(mean(x^2) + eps)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def test_rms_norm_closed_forms():
+    # a constant row c: mean square c^2, so y = c w / sqrt(c^2 + eps)
+    w = np.array([1.0, -2.0, 0.5, 3.0])
+    y = oracle.rms_norm(np.full((1, 4), 3.0), w, 0.25)
+    assert np.allclose(y, 3.0 * w / math.sqrt(9.25), rtol=0, atol=1e-15)
+    # (3, 4): mean square 12.5
+    y = oracle.rms_norm([[3.0, 4.0]], [1.0, 1.0], 0.0)
+    assert np.allclose(y, [[3 / math.sqrt(12.5), 4 / math.sqrt(12.5)]],
+                       rtol=0, atol=1e-15)
+    # one element: y = sign(x) w when eps = 0
+    assert oracle.rms_norm([[-7.0]], [2.0], 0.0)[0, 0] == -2.0
+    # a zero row stays zero for eps > 0
+    assert np.all(oracle.rms_norm(np.zeros((1, 9)), np.ones(9), 1e-6) == 0)
+
+
+def test_rms_norm_invariants():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((5, 77)) * rng.uniform(0.1, 10, (5, 1))
+    ones = np.ones(77)
+    y = oracle.rms_norm(x, ones, 0.0)
+    # unit weights, eps 0: every row has mean square exactly 1
+    assert np.allclose(np.mean(y * y, axis=1), 1.0, rtol=1e-13)
+    # scale invariance per row, weights act per column
+    assert np.allclose(oracle.rms_norm(x * 17.0, ones, 0.0), y, rtol=1e-13)
+    w = rng.standard_normal(77)
+    assert np.allclose(oracle.rms_norm(x, w, 0.0), y * w, rtol=1e-13)
+    # rows are independent
+    assert np.allclose(oracle.rms_norm(x[2:3], w, 0.3),
+                       oracle.rms_norm(x, w, 0.3)[2:3], rtol=1e-15)
+    # eps enters the mean square, not the root: the mean square of the
+    # result is m / (m + eps) for unit weights
+    m = np.mean(x * x, axis=1)
+    y = oracle.rms_norm(x, ones, 0.5)
+    assert np.allclose(np.mean(y * y, axis=1), m / (m + 0.5), rtol=1e-13)
+
+
+def test_rms_norm_brute_force_small():
+    rng = np.random.default_rng(2)
+    x = rng.integers(-5, 6, (3, 6)).astype(float)
+    w = rng.integers(-3, 4, 6).astype(float)
+    y = oracle.rms_norm(x, w, 0.125)
+    for r in range(3):
+        s = 0.0
+        for j in range(6):
+            s += x[r, j] ** 2
+        d = math.sqrt(s / 6 + 0.125)
+        for j in range(6):
+            assert abs(y[r, j] - x[r, j] * w[j] / d) <= 1e-15 * (1 + abs(y[r, j]))
