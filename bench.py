@@ -406,6 +406,73 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
     return out
 
 
+def bench_exec_modes(args, tg, n_elems=2048, chain=(1, 10, 100, 1000),
+                     reps=20):
+    """Host launch cost per operation of a chain of N element-wise products
+    y_i = y_(i-1) * g over one 2048-element bf16 tile, in three modes:
+    sync (launch, then wait for the stream, per operation), chained (N
+    launches, one wait) and graph (the N launches captured once, one replay
+    and one wait).  Launches go through the C ABI with descriptors built
+    once (checked launches: the ownership rules run on the host per call).
+    Per-operation microseconds: minimum and 75th percentile over `reps`."""
+    import ctypes
+    import time
+    g = synth.to_bf16(1.0 + synth.normal((1, n_elems), 81, std=1e-3)).cuda()
+    bufs = [synth.to_bf16(synth.normal((1, n_elems), 82)).cuda(),
+            torch.empty((1, n_elems), dtype=torch.bfloat16, device="cuda")]
+    din = [tg.make_in(b) for b in bufs]
+    dout = [tg.make_out(b) for b in bufs]
+    dg = tg.make_in(g)
+    opts = tg.make_opts()
+
+    def launch(i, stream):
+        st = tg.lib.tile_mul(din[i & 1], dg, dout[(i + 1) & 1], opts, stream)
+        if st:
+            raise tg.TileGemmError(st, tg.last_error())
+
+    out = []
+    cur = torch.cuda.current_stream()
+    for n in chain:
+        res = {"N": n}
+        for mode in ("sync", "chained", "graph"):
+            if mode == "graph":
+                gr = torch.cuda.CUDAGraph()
+                s = torch.cuda.Stream()
+                with torch.cuda.stream(s):
+                    for i in range(n):
+                        launch(i, s.cuda_stream)
+                torch.cuda.synchronize()
+                with torch.cuda.stream(s):
+                    with torch.cuda.graph(gr, stream=s):
+                        for i in range(n):
+                            launch(i, s.cuda_stream)
+                torch.cuda.synchronize()
+            times = []
+            for r in range(reps + 2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "sync":
+                    for i in range(n):
+                        launch(i, cur.cuda_stream)
+                        cur.synchronize()
+                elif mode == "chained":
+                    for i in range(n):
+                        launch(i, cur.cuda_stream)
+                    cur.synchronize()
+                else:
+                    gr.replay()
+                    torch.cuda.current_stream().synchronize()
+                    torch.cuda.synchronize()
+                t = (time.perf_counter() - t0) * 1e6 / n
+                if r >= 2:
+                    times.append(t)
+            res[mode] = {"us_per_op_min": float(np.min(times)),
+                         "us_per_op_p75": float(np.percentile(times, 75))}
+        out.append(res)
+        log("exec modes", res)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,6 +487,9 @@ def main():
                     help="only the decode-shaped products (one JSON line)")
     ap.add_argument("--add", action="store_true",
                     help="only the element-wise add (one JSON line)")
+    ap.add_argument("--exec-modes", action="store_true",
+                    help="only the launch-mode sweep (sync / chained / "
+                         "graph, N = 1..1000)")
     ap.add_argument("--layer", action="store_true",
                     help="only the decode layer rms_norm -> matvec -> add")
     ap.add_argument("--library-reference", action="store_true",
@@ -454,6 +524,10 @@ def main():
         print(json.dumps({"decode_layer": bench_decode_layer(args, tg)}),
               flush=True)
         return
+    if args.exec_modes:
+        print(json.dumps({"exec_modes": bench_exec_modes(args, tg)}),
+              flush=True)
+        return
 
     res = bench_bf16_main(args, tg)
     extra = {"ms_unchecked_launch": res["ms_unchecked"],
@@ -466,6 +540,7 @@ def main():
         extra["bf16_8192_b_row_major"] = bench_bf16_kn(args, tg)
         extra["elementwise_add"] = bench_add(args, tg)
         extra["decode_layer"] = bench_decode_layer(args, tg)
+        extra["exec_modes"] = bench_exec_modes(args, tg)
     if args.picker:
         from paper_2606_15991_amd import picker
         import io

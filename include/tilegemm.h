@@ -265,6 +265,19 @@ tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
                    const tg_opts *opts, tg_stream stream);
 
 /*
+ * tile_mul -- z = x * y element by element: the element-wise kernel of the
+ * execution-mode measurement of Sec. 5.2 (y = x . g over one tile).
+ * Arguments, partition, checks, errors and ownership as tile_add.  Each
+ * product is formed in binary32 and rounded once to the dtype: for TG_F32
+ * and for bf16 products of magnitude >= 2^-126 that is the correctly
+ * rounded product; smaller bf16 products are rounded first to the binary32
+ * subnormal grid (2^-149), then to bf16 (error <= 2^-133, one bf16
+ * subnormal step, instead of 2^-134).
+ */
+tg_status tile_mul(const tg_in *x, const tg_in *y, tg_out *z,
+                   const tg_opts *opts, tg_stream stream);
+
+/*
  * tile_rms_norm -- y = x * w / sqrt(mean(x^2) + eps) row by row: the RMS
  * normalisation that opens the decode layer of Sec. 3.2's graph-scope
  * listing (partitioned [1, d]: each program owns whole rows).

@@ -24,6 +24,11 @@ What it computes (arxiv 2606.15991):
     two binary32 values, rounded again to the 8- or 24-bit format, is that
     correctly rounded sum (53 >= 2p + 2, so the double rounding is
     innocuous).
+  * mul_bf16 / mul_f32 -- the element-wise product of the execution-mode
+    measurement of Sec. 5.2, correctly rounded.  The binary64 product of
+    two bf16 values (8-bit significands, exponents within binary64's range)
+    or two binary32 values (24-bit significands: 48 bits) is exact, so one
+    rounding to the storage format is the definition.
   * rms_norm -- the RMS normalisation of the decode layer in Sec. 3.2's
     graph-scope listing, y = x * w / sqrt(mean(x^2) + eps) per row, in
     binary64 (the usual RMSNorm definition; the paper names the operation
@@ -201,6 +206,21 @@ def rms_norm(x, w, eps: float) -> np.ndarray:
     w = np.asarray(w, dtype=np.float64).reshape(-1)
     ms = np.mean(x * x, axis=1, keepdims=True)
     return x * w / np.sqrt(ms + float(eps))
+
+
+def mul_bf16(x_bits, y_bits) -> np.ndarray:
+    """z = x * y for bfloat16 bit patterns: the correctly rounded product
+    (the binary64 product of two 8-bit significands is exact)."""
+    with np.errstate(invalid="ignore", over="ignore", under="ignore"):
+        return round_bf16(decode_bf16(x_bits) * decode_bf16(y_bits))
+
+
+def mul_f32(x, y) -> np.ndarray:
+    """z = x * y for binary32 arrays: the correctly rounded product (the
+    binary64 product of two 24-bit significands is exact)."""
+    with np.errstate(over="ignore", invalid="ignore", under="ignore"):
+        s = np.asarray(x, np.float64) * np.asarray(y, np.float64)
+        return s.astype(np.float32)
 
 
 def partition_paint(M, N, bm, bn, prog_offsets=None, prog_tiles=None):

@@ -104,6 +104,8 @@ def _load():
                                              P(tg_opts)]
     lib.tile_add.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                              ctypes.c_void_p]
+    lib.tile_mul.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
+                             ctypes.c_void_p]
     lib.tile_rms_norm.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
                                   P(tg_out), P(tg_opts), ctypes.c_void_p]
     lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
@@ -168,7 +170,8 @@ def _load():
         getattr(lib, f).restype = i32
     for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
               "tile_gemm_grouped_prepare", "tile_gemm_grouped",
-              "tile_add", "tile_rms_norm", "tile_error_norm"):
+              "tile_add", "tile_mul", "tile_rms_norm",
+              "tile_error_norm"):
         getattr(lib, f).restype = i32
     return lib
 
@@ -298,6 +301,17 @@ def tile_add(x, y, z, bm=0, bn=0, *, checked=True, write_count=None,
     o = make_opts(write_count=write_count, checked=checked)
     _raise(lib.tile_add(make_in(x), make_in(y), dz, o, _stream(stream)))
     tile_add.last_partition = (dz.bm, dz.bn)
+    return z
+
+
+def tile_mul(x, y, z, bm=0, bn=0, *, checked=True, write_count=None,
+             stream=None):
+    """z = x * y element by element into z's bm x bn partition (bf16 or
+    fp32).  Returns z."""
+    dz = make_out(z, bm, bn)
+    o = make_opts(write_count=write_count, checked=checked)
+    _raise(lib.tile_mul(make_in(x), make_in(y), dz, o, _stream(stream)))
+    tile_mul.last_partition = (dz.bm, dz.bn)
     return z
 
 

@@ -66,6 +66,23 @@ struct AddTraits<TG_BF16> {
         }
         return uint4{w[0], w[1], w[2], w[3]};
     }
+    // eight bf16 products: the binary32 product of two 8-bit significands
+    // is exact unless it falls below the binary32 normal range
+    __device__ static uint4 mul16(const uint4 &a, const uint4 &b) {
+        const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
+        const uint32_t wb[4] = {b.x, b.y, b.z, b.w};
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float lo = __uint_as_float(wa[q] << 16) *
+                             __uint_as_float(wb[q] << 16);
+            const float hi = __uint_as_float(wa[q] & 0xffff0000u) *
+                             __uint_as_float(wb[q] & 0xffff0000u);
+            w[q] = (uint32_t)f32_to_bf16_bits(lo) |
+                   ((uint32_t)f32_to_bf16_bits(hi) << 16);
+        }
+        return uint4{w[0], w[1], w[2], w[3]};
+    }
     // sum of the squares of the eight values of a chunk
     __device__ static float sumsq16(const uint4 &a) {
         const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
@@ -111,6 +128,12 @@ struct AddTraits<TG_F32> {
                      __float_as_uint(__uint_as_float(a.z) + __uint_as_float(b.z)),
                      __float_as_uint(__uint_as_float(a.w) + __uint_as_float(b.w))};
     }
+    __device__ static uint4 mul16(const uint4 &a, const uint4 &b) {
+        return uint4{__float_as_uint(__uint_as_float(a.x) * __uint_as_float(b.x)),
+                     __float_as_uint(__uint_as_float(a.y) * __uint_as_float(b.y)),
+                     __float_as_uint(__uint_as_float(a.z) * __uint_as_float(b.z)),
+                     __float_as_uint(__uint_as_float(a.w) * __uint_as_float(b.w))};
+    }
     __device__ static float sumsq16(const uint4 &a) {
         const float v[4] = {__uint_as_float(a.x), __uint_as_float(a.y),
                             __uint_as_float(a.z), __uint_as_float(a.w)};
@@ -128,8 +151,21 @@ struct AddTraits<TG_F32> {
     }
 };
 
-template <int DT, bool VEC>
-__global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
+// The binary operation of the element-wise kernels: z = x + y (MUL false)
+// or z = x * y (MUL true), one binary32 operation rounded once.
+template <int DT, bool MUL>
+__device__ __forceinline__ uint4 op16(const uint4 &a, const uint4 &b) {
+    if constexpr (MUL) return AddTraits<DT>::mul16(a, b);
+    else return AddTraits<DT>::add16(a, b);
+}
+template <bool MUL>
+__device__ __forceinline__ float op1(float a, float b) {
+    if constexpr (MUL) return a * b;
+    else return a + b;
+}
+
+template <int DT, bool VEC, bool MUL>
+__device__ __forceinline__ void elementwise_body(const AddArgs &g) {
     using T = AddTraits<DT>;
     constexpr int EPC = 16 / T::ES;               // elements per chunk
     const int64_t tiles_n = (g.cols + g.bn - 1) / g.bn;
@@ -178,7 +214,7 @@ __global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
                     const int64_t q = base + (int64_t)u * kAddThreads;
                     if (q < total)
                         st16_stream(static_cast<char *>(g.z) + off[u][2],
-                                    T::add16(a[u], b[u]));
+                                    op16<DT, MUL>(a[u], b[u]));
                 }
             }
             const int64_t rest = nc - cpr * EPC;
@@ -186,15 +222,15 @@ __global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
                 const int64_t r = r0 + q / rest;
                 const int64_t c = c0 + cpr * EPC + q % rest;
                 T::store(g.z, r * g.ldz + c,
-                         T::load(g.x, r * g.ldx + c) +
-                             T::load(g.y, r * g.ldy + c));
+                         op1<MUL>(T::load(g.x, r * g.ldx + c),
+                                  T::load(g.y, r * g.ldy + c)));
             }
         } else {
             for (int64_t q = threadIdx.x; q < nr * nc; q += kAddThreads) {
                 const int64_t r = r0 + q / nc, c = c0 + q % nc;
                 T::store(g.z, r * g.ldz + c,
-                         T::load(g.x, r * g.ldx + c) +
-                             T::load(g.y, r * g.ldy + c));
+                         op1<MUL>(T::load(g.x, r * g.ldx + c),
+                                  T::load(g.y, r * g.ldy + c)));
             }
         }
         if (g.wcount) {
@@ -203,6 +239,16 @@ __global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
                 atomicAdd(&g.wcount[(r0 + q / nc) * g.cols + c0 + q % nc], 1);
         }
     }
+}
+
+template <int DT, bool VEC>
+__global__ __launch_bounds__(kAddThreads) void add_kernel(AddArgs g) {
+    elementwise_body<DT, VEC, false>(g);
+}
+
+template <int DT, bool VEC>
+__global__ __launch_bounds__(kAddThreads) void mul_kernel(AddArgs g) {
+    elementwise_body<DT, VEC, true>(g);
 }
 
 // RMS normalisation (the first step of the decode layer of Sec. 3.2's
@@ -313,6 +359,29 @@ hipError_t launch_rms_norm(const NormArgs &a, bool vec, int programs,
         launch_norm_dt<TG_F32>(a, vec, dim3(programs), st);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_mul(const AddArgs &a, bool vec, int programs,
+                      hipStream_t st) {
+    dim3 grid(programs), block(kAddThreads);
+    if (a.dtype == TG_BF16) {
+        if (vec)
+            hipLaunchKernelGGL((mul_kernel<TG_BF16, true>), grid, block, 0,
+                               st, a);
+        else
+            hipLaunchKernelGGL((mul_kernel<TG_BF16, false>), grid, block, 0,
+                               st, a);
+    } else if (a.dtype == TG_F32) {
+        if (vec)
+            hipLaunchKernelGGL((mul_kernel<TG_F32, true>), grid, block, 0, st,
+                               a);
+        else
+            hipLaunchKernelGGL((mul_kernel<TG_F32, false>), grid, block, 0,
+                               st, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

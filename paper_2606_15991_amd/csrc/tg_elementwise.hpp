@@ -22,6 +22,9 @@ struct AddArgs {
 };
 hipError_t launch_add(const AddArgs &a, bool vec, int programs,
                       hipStream_t st);
+// Element-wise z = x * y, same arguments.
+hipError_t launch_mul(const AddArgs &a, bool vec, int programs,
+                      hipStream_t st);
 
 // y = x * w / sqrt(mean(x^2) + eps) per row, over y's bm x cols partition.
 struct NormArgs {

@@ -941,8 +941,9 @@ tg_status tile_gemm_grouped(void *ws, tg_stream stream) {
     return e == hipSuccess ? TG_OK : hip_fail(e, "grouped kernel launch");
 }
 
-tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
-                   const tg_opts *opts, tg_stream stream) {
+namespace {
+tg_status tile_elementwise(bool mul, const tg_in *x, const tg_in *y,
+                           tg_out *z, const tg_opts *opts, tg_stream stream) {
     g_err.clear();
     tg_status st;
     if ((st = check_in(x, "x")) != TG_OK) return st;
@@ -994,9 +995,20 @@ tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
     // 2^28 bf16 elements: 4 % ahead of four per unit)
     const int programs =
         (int)std::min<int64_t>(tiles, (int64_t)std::max(cus, 1) * 16);
-    hipError_t e = launch_add(a, vec, programs,
-                              static_cast<hipStream_t>(stream));
+    hipError_t e = (mul ? launch_mul : launch_add)(
+        a, vec, programs, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? TG_OK : hip_fail(e, "element-wise launch");
+}
+}  // namespace
+
+tg_status tile_add(const tg_in *x, const tg_in *y, tg_out *z,
+                   const tg_opts *opts, tg_stream stream) {
+    return tile_elementwise(false, x, y, z, opts, stream);
+}
+
+tg_status tile_mul(const tg_in *x, const tg_in *y, tg_out *z,
+                   const tg_opts *opts, tg_stream stream) {
+    return tile_elementwise(true, x, y, z, opts, stream);
 }
 
 tg_status tile_rms_norm(const tg_in *x, const tg_in *w, float eps,

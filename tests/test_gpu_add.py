@@ -165,3 +165,54 @@ def test_add_rejects_aliasing_and_mismatch():
         tg.tile_add(e, e.clone(), torch.empty_like(e))
     torch.cuda.synchronize()
     assert float(x.float().sum()) == 64 * 64
+
+
+# ------------------------------------------------------------ z = x * y
+
+def run_mul(x, y, bm=0, bn=0, count=False):
+    xd, yd = x.to(DEV), y.to(DEV)
+    z = torch.full(x.shape, 7.0, dtype=x.dtype, device=DEV)
+    wc = torch.zeros(x.shape, dtype=torch.int32, device=DEV) if count else None
+    tg.tile_mul(xd, yd, z, bm, bn, write_count=wc)
+    torch.cuda.synchronize()
+    return z, wc
+
+
+@pytest.mark.parametrize("shape", [(1, 2048), (3, 1000), (257, 1031),
+                                   (2, 70000)])
+def test_mul_bf16_random_codes(shape):
+    """Bit-exact where the exact product is 0, infinite, NaN or at least
+    2^-126 in magnitude; below that the product is first rounded to the
+    binary32 subnormal grid, and the result is within 2^-133 (one bf16
+    subnormal step) of the exact product."""
+    note("mul codes bf16", shape)
+    x, y = codes_bf16(shape, 13), codes_bf16(shape, 31)
+    z, _ = run_mul(x, y)
+    xb, yb = bits16(x), bits16(y)
+    exact = oracle.decode_bf16(xb) * oracle.decode_bf16(yb)
+    want = oracle.mul_bf16(xb, yb)
+    got = bits16(z)
+    dg = oracle.decode_bf16(got)
+    small = (np.abs(exact) < 2.0 ** -126) & (exact != 0)
+    nan_w = np.isnan(oracle.decode_bf16(want))
+    assert np.array_equal(np.isnan(dg), nan_w)
+    big = ~small & ~nan_w
+    assert np.array_equal(got[big], want[big])
+    assert np.all(np.abs(dg[small] - exact[small]) <= 2.0 ** -133)
+
+
+@pytest.mark.parametrize("shape", [(1, 2048), (257, 1031)])
+def test_mul_f32_random_codes_bit_exact(shape):
+    note("mul codes f32", shape)
+    x, y = codes_f32(shape, 17), codes_f32(shape, 37)
+    z, _ = run_mul(x, y)
+    assert_same(z, oracle.mul_f32(x.numpy(), y.numpy()))
+
+
+def test_mul_normal_values_partition_bit_exact():
+    note("mul normal, partition 5 x 40")
+    x = synth.to_bf16(synth.normal((129, 1000), 43))
+    y = synth.to_bf16(synth.normal((129, 1000), 44))
+    z, wc = run_mul(x, y, 5, 40, count=True)
+    assert_same(z, oracle.mul_bf16(bits16(x), bits16(y)))
+    assert int(wc.min()) == 1 and int(wc.max()) == 1

@@ -125,3 +125,47 @@ def test_add_f32_is_ieee_binary32_addition():
     assert np.array_equal(np.isnan(got), nan)
     assert np.array_equal(got[~nan].view(np.uint32),
                           want[~nan].view(np.uint32))
+
+
+def test_mul_bf16_pinned_cases():
+    b = lambda v: oracle.round_bf16(np.asarray(v, dtype=np.float64))
+    mul = lambda x, y: int(np.ravel(oracle.mul_bf16(b(x), b(y)))[0])
+    ints = np.arange(-15, 16, dtype=np.float64)
+    x, y = np.meshgrid(ints, ints)
+    z = oracle.mul_bf16(oracle.round_bf16(x), oracle.round_bf16(y))
+    assert np.array_equal(_dec(z), x * y)        # |x y| <= 225: 8 bits
+    # (1 + 2^-7)^2 = 1 + 2^-6 + 2^-14: rounds to 1 + 2^-6
+    assert mul(1 + 2.0 ** -7, 1 + 2.0 ** -7) == 0x3F82
+    # (1 + 3 * 2^-7)(1 + 2^-7) = 1 + 2^-5 + 3 * 2^-14 -> 1 + 2^-5
+    assert mul(1 + 3 * 2.0 ** -7, 1 + 2.0 ** -7) == 0x3F84
+    assert mul(2.0 ** -70, 2.0 ** -70) == 0x0000    # 2^-140 < 2^-134
+    assert mul(2.0 ** -66, 2.0 ** -67) == 0x0001    # 2^-133
+    assert mul(2.0 ** 64, 2.0 ** 64) == 0x7F80      # 2^128 overflows
+    assert mul(-0.0, 5.0) == 0x8000
+    assert np.isnan(_dec(oracle.mul_bf16(0x7F80, 0x0000)))   # inf * 0
+
+
+def test_mul_bf16_identities_over_every_code():
+    dec = _dec(ALL)
+    ok = ~np.isnan(dec)
+    one = np.full_like(ALL, 0x3F80)
+    assert np.array_equal(oracle.mul_bf16(ALL, one)[ok], ALL[ok])
+    m1 = np.full_like(ALL, 0xBF80)
+    assert np.array_equal(oracle.mul_bf16(ALL, m1)[ok],
+                          (ALL ^ np.uint16(0x8000))[ok])
+    two = np.full_like(ALL, 0x4000)
+    fin = ok & (np.abs(dec) < 2.0 ** 127)
+    assert np.array_equal(_dec(oracle.mul_bf16(ALL, two))[fin], 2 * dec[fin])
+
+
+def test_mul_f32_is_ieee_binary32_multiplication():
+    rng = np.random.default_rng(12)
+    bits = rng.integers(0, 2 ** 32, (2, 200000), dtype=np.uint64)
+    x, y = bits.astype(np.uint32).view(np.float32)
+    with np.errstate(over="ignore", invalid="ignore", under="ignore"):
+        want = x * y
+    got = oracle.mul_f32(x, y)
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan].view(np.uint32),
+                          want[~nan].view(np.uint32))
