@@ -473,6 +473,79 @@ def bench_exec_modes(args, tg, n_elems=2048, chain=(1, 10, 100, 1000),
     return out
 
 
+def bench_bimodal(args, tg, n=2000, stream_counts=(1, 2, 4, 8, 16, 32),
+                  reps=5):
+    """A queue of n GEMMs, 80 % 512^3 and 20 % 2048^3 (bf16, weights
+    stored N x K, binary32 output), run (a) as single launches fanned out
+    round-robin over S streams, launched eagerly from Python and captured
+    in one graph, for each S in stream_counts, and (b) as one grouped
+    persistent launch.  Throughput in GEMMs per millisecond (median of
+    reps wall-clock runs, each bracketed by device synchronisation)."""
+    sizes = synth.bimodal_sizes(96, n)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(97)
+    As = [torch.randn((s, s), device="cuda", generator=gen).bfloat16()
+          for s in sizes]
+    Bs = [torch.randn((s, s), device="cuda", generator=gen).bfloat16()
+          for s in sizes]
+    Cs = [torch.empty((s, s), device="cuda") for s in sizes]
+    flops = sum(2.0 * s ** 3 for s in sizes)
+
+    def wall(fn):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ts))
+
+    fan = []
+    for S in stream_counts:
+        streams = [torch.cuda.Stream() for _ in range(S)]
+
+        def fan_out():
+            for i in range(n):
+                tg.tile_gemm(As[i], Bs[i], Cs[i], b_trans=True,
+                             checked=False, stream=streams[i % S])
+        fan_out()
+        ms_eager = wall(fan_out)
+        # the same fan-out captured in one graph (fork from and join into
+        # the capture stream through events)
+        cap = torch.cuda.Stream()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(cap):
+            with torch.cuda.graph(g, stream=cap):
+                ev = torch.cuda.Event()
+                ev.record(cap)
+                for st in streams:
+                    st.wait_event(ev)
+                fan_out()
+                for st in streams:
+                    e = torch.cuda.Event()
+                    e.record(st)
+                    cap.wait_event(e)
+        torch.cuda.synchronize()
+        g.replay()
+        ms_graph = wall(g.replay)
+        fan.append({"streams": S, "eager_ms": ms_eager,
+                    "eager_gemm_per_ms": n / ms_eager, "graph_ms": ms_graph,
+                    "graph_gemm_per_ms": n / ms_graph})
+        log("bimodal fan-out", fan[-1])
+        del g
+    launch = tg.tile_gemm_grouped_prepare(As, Bs, Cs, b_trans=True)
+    tg.tile_gemm_grouped(launch)
+    ms_grouped = wall(lambda: tg.tile_gemm_grouped(launch))
+    out = {"gemms": n, "big_fraction": sizes.count(2048) / n,
+           "fan_out": fan,
+           "grouped": {"ms": ms_grouped, "gemm_per_ms": n / ms_grouped,
+                       "tflops": flops / (ms_grouped * 1e-3) / 1e12}}
+    log("bimodal grouped", out["grouped"])
+    del As, Bs, Cs, launch
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -490,6 +563,8 @@ def main():
     ap.add_argument("--exec-modes", action="store_true",
                     help="only the launch-mode sweep (sync / chained / "
                          "graph, N = 1..1000)")
+    ap.add_argument("--bimodal", action="store_true",
+                    help="only the bimodal GEMM queue (fan-out vs grouped)")
     ap.add_argument("--layer", action="store_true",
                     help="only the decode layer rms_norm -> matvec -> add")
     ap.add_argument("--library-reference", action="store_true",
@@ -524,6 +599,10 @@ def main():
         print(json.dumps({"decode_layer": bench_decode_layer(args, tg)}),
               flush=True)
         return
+    if args.bimodal:
+        print(json.dumps({"bimodal_queue": bench_bimodal(args, tg)}),
+              flush=True)
+        return
     if args.exec_modes:
         print(json.dumps({"exec_modes": bench_exec_modes(args, tg)}),
               flush=True)
@@ -541,6 +620,7 @@ def main():
         extra["elementwise_add"] = bench_add(args, tg)
         extra["decode_layer"] = bench_decode_layer(args, tg)
         extra["exec_modes"] = bench_exec_modes(args, tg)
+        extra["bimodal_queue"] = bench_bimodal(args, tg)
     if args.picker:
         from paper_2606_15991_amd import picker
         import io

@@ -122,3 +122,10 @@ def random_codes16(shape, seed: int) -> torch.Tensor:
     exponent, both zeros, subnormals, infinities and NaNs."""
     return torch.randint(-32768, 32768, shape, generator=gen(seed),
                          dtype=torch.int32).to(torch.int16)
+
+
+def bimodal_sizes(seed: int, n: int = 2000, p_big: float = 0.2,
+                  small: int = 512, big: int = 2048):
+    """n square GEMM sizes: `big` with probability p_big, else `small`."""
+    u = torch.rand(n, generator=gen(seed))
+    return [big if float(v) < p_big else small for v in u]

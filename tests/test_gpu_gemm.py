@@ -706,3 +706,34 @@ def test_every_fp8_variant(M, N, K):
                      config=cfg, scale_a=sad, scale_b=sbd)
         torch.cuda.synchronize()
         assert rel_err(_pick(C, rows), Rq) <= FP8_BAR, cfg
+
+
+def test_bimodal_queue_grouped_matches_single_and_oracle():
+    """A 40-GEMM queue with the bimodal size mix (512^3 / 2048^3, 80/20),
+    weights stored N x K: one grouped launch equals the single launches of
+    the same configuration bit for bit, and sampled entries match the
+    oracle."""
+    sizes = synth.bimodal_sizes(95, 40)
+    assert 2048 in sizes and 512 in sizes
+    note("bimodal grouped", sizes)
+    As = [dev(synth.to_bf16(synth.normal((s, s), 500 + i)))
+          for i, s in enumerate(sizes)]
+    Bs = [dev(synth.to_bf16(synth.normal((s, s), 600 + i)))
+          for i, s in enumerate(sizes)]
+    Cs = [torch.full((s, s), float("nan"), device=DEV) for s in sizes]
+    launch = tg.tile_gemm_grouped_prepare(As, Bs, Cs, b_trans=True,
+                                          config={"bm": 256, "bn": 256})
+    tg.tile_gemm_grouped(launch)
+    torch.cuda.synchronize()
+    g = torch.Generator().manual_seed(3)
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        s = sizes[i]
+        single = torch.empty_like(C)
+        tg.tile_gemm(A, B, single, 256, 256, b_trans=True)
+        torch.cuda.synchronize()
+        assert torch.equal(single, C), i
+        ii = torch.randint(0, s, (512,), generator=g).numpy()
+        jj = torch.randint(0, s, (512,), generator=g).numpy()
+        R = reference_entries(A.cpu(), B.cpu(), ii, jj, b_trans=True)
+        got = C.cpu().numpy()[ii, jj].astype(np.float64)
+        assert np.linalg.norm(got - R) <= 1e-5 * np.linalg.norm(R), i
