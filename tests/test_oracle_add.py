@@ -169,3 +169,43 @@ def test_mul_f32_is_ieee_binary32_multiplication():
     assert np.array_equal(np.isnan(got), nan)
     assert np.array_equal(got[~nan].view(np.uint32),
                           want[~nan].view(np.uint32))
+
+
+def _round_variant(kind):
+    """Plausible mistakes in bf16 rounding, planted on the CPU."""
+    def f(v):
+        v = np.asarray(v, dtype=np.float64)
+        _, e = np.frexp(v)
+        shift = {"quantum_off_by_one": -7}.get(kind, -8)
+        q = np.ldexp(1.0, np.maximum(e.astype(np.int64) + shift, -133))
+        with np.errstate(over="ignore", invalid="ignore"):
+            if kind == "ties_away":
+                r = np.sign(v) * np.floor(np.abs(v) / q + 0.5) * q
+            elif kind == "truncate":
+                r = np.trunc(v / q) * q
+            elif kind == "no_subnormal_floor":
+                q = np.ldexp(1.0, e.astype(np.int64) - 8)
+                r = np.round(v / q) * q
+                r = np.where(np.abs(r) < 2.0 ** -126, 0.0, r)
+            else:
+                r = np.round(v / q) * q
+            r = np.where(np.abs(r) >= 2.0 ** 128, np.copysign(np.inf, v), r)
+            return (r.astype(np.float32).view(np.uint32) >> 16).astype(
+                np.uint16)
+    return f
+
+
+@pytest.mark.parametrize("kind", ["ties_away", "truncate",
+                                  "quantum_off_by_one", "no_subnormal_floor"])
+def test_planted_rounding_mistakes_fail_a_pin(kind):
+    f = _round_variant(kind)
+    dec = _dec(ALL)
+    fin = np.isfinite(dec)
+    lo, hi = POS_FINITE[:-1], POS_FINITE[1:]
+    mid = (_dec(lo) + _dec(hi)) / 2
+    rng = np.random.default_rng(7)
+    v = np.ldexp(rng.random(5000) + 0.5, rng.integers(-140, 128, 5000))
+    caught = (not np.array_equal(f(dec[fin]), ALL[fin])
+              or not np.array_equal(f(mid), np.where(lo % 2 == 0, lo, hi))
+              or not np.array_equal(f(v), oracle.round_bf16(v)))
+    assert caught

@@ -56,3 +56,41 @@ def test_rms_norm_brute_force_small():
         d = math.sqrt(s / 6 + 0.125)
         for j in range(6):
             assert abs(y[r, j] - x[r, j] * w[j] / d) <= 1e-15 * (1 + abs(y[r, j]))
+
+
+def _norm_variant(kind):
+    """Plausible mistakes in the RMS normalisation, planted on the CPU."""
+    def f(x, w, eps):
+        x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+        w = np.asarray(w, dtype=np.float64).reshape(-1)
+        if kind == "sum_not_mean":
+            return x * w / np.sqrt(np.sum(x * x, axis=1, keepdims=True) + eps)
+        if kind == "eps_outside_root":
+            return x * w / (np.sqrt(np.mean(x * x, axis=1, keepdims=True))
+                            + eps)
+        if kind == "no_weight":
+            return x / np.sqrt(np.mean(x * x, axis=1, keepdims=True) + eps)
+        if kind == "column_mean":
+            return x * w / np.sqrt(np.mean(x * x, axis=0, keepdims=True) + eps)
+        return oracle.rms_norm(x, w, eps)
+    return f
+
+
+@pytest.mark.parametrize("kind", ["sum_not_mean", "eps_outside_root",
+                                  "no_weight", "column_mean"])
+def test_planted_norm_mistakes_fail_a_pin(kind):
+    f = _norm_variant(kind)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((5, 77)) * rng.uniform(0.1, 10, (5, 1))
+    ones = np.ones(77)
+    w = rng.standard_normal(77)
+    m = np.mean(x * x, axis=1)
+    checks = [
+        np.allclose(f(np.full((1, 4), 3.0), [1.0, -2.0, 0.5, 3.0], 0.25),
+                    3.0 * np.array([1.0, -2.0, 0.5, 3.0]) / math.sqrt(9.25)),
+        np.allclose(np.mean(f(x, ones, 0.0) ** 2, axis=1), 1.0),
+        np.allclose(np.mean(f(x, ones, 0.5) ** 2, axis=1), m / (m + 0.5)),
+        np.allclose(f(x, w, 0.0), f(x, ones, 0.0) * w),
+        np.allclose(f(x[2:3], w, 0.3), f(x, w, 0.3)[2:3]),
+    ]
+    assert not all(checks)
