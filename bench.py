@@ -378,7 +378,8 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
     """The decode layer rms_norm -> matvec (d x d bf16 weights stored N x K)
     -> residual add at M = 1, over `layers` layers with weights of their own
     (16 x 52 MB, more than the Infinity Cache holds), launched eagerly and
-    as one captured graph; time per layer and weight-stream GB/s."""
+    as one captured graph, and with the normalisation fused into the
+    matvec (two kernels per layer); time per layer and weight-stream GB/s."""
     xs = synth.to_bf16(synth.normal((1, d), 71)).cuda()
     nw = (1.0 + synth.normal((d,), 72, std=0.1)).to(torch.bfloat16).cuda()
     Ws = [synth.to_bf16(synth.normal((d, d), 100 + i, std=0.02)).cuda()
@@ -395,13 +396,23 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
                          stream=stream)
             tg.tile_add(h, q, res, checked=False, stream=stream)
             h = res
+    def run_fused(stream=None):
+        h = xs
+        for i in range(layers):
+            norm, q, res = bufs[3 * i:3 * i + 3]
+            tg.tile_rms_norm_matvec(h, nw, Ws[i], q, 1e-6, checked=False,
+                                    stream=stream)
+            tg.tile_add(h, q, res, checked=False, stream=stream)
+            h = res
     ms_eager = timed(run, 20, 5)
     ms_graph = graph_ms([lambda st: run(stream=st)], reps=20)
+    ms_fused = graph_ms([lambda st: run_fused(stream=st)], reps=20)
     wbytes = 2.0 * d * d
     out = {"d": d, "layers": layers,
            "us_per_layer_eager": ms_eager * 1e3 / layers,
            "us_per_layer_graph": ms_graph * 1e3 / layers,
-           "weight_gbs_graph": wbytes * layers / (ms_graph * 1e-3) / 1e9}
+           "weight_gbs_graph": wbytes * layers / (ms_graph * 1e-3) / 1e9,
+           "us_per_layer_graph_fused_norm": ms_fused * 1e3 / layers}
     log("decode layer", out)
     return out
 

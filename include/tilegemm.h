@@ -297,6 +297,25 @@ tg_status tile_rms_norm(const tg_in *x, const tg_in *w, float eps, tg_out *y,
                         const tg_opts *opts, tg_stream stream);
 
 /*
+ * tile_rms_norm_matvec -- the decode layer's normalisation fused into its
+ * product (Sec. 3.2, graph-scope listing: rms_norm then matvec):
+ * y = diag(1 / sqrt(mean_k x[m,k]^2 + eps)) . (x * nw) . W^T for M <= 16
+ * activation rows.  x: device bf16 M x K; nw: device bf16 1 x K
+ * normalisation weights, 16-byte aligned; W: device, stored N x K
+ * (trans = 1), bf16 or E4M3 (then opts->scale_b holds its N row scales);
+ * y: device M x N, f32 or bf16, partition chosen by the decode kernel
+ * (16 x 16 or 16 x 32, written back into *y).  Each x * nw is rounded to
+ * bf16 before the contraction; sums of squares and the product accumulate
+ * in binary32; the row scale multiplies the binary32 sum.  opts may be NULL;
+ * precision and config must be unset.  Errors as tile_gemm, before anything
+ * is enqueued.  y is exclusively borrowed until the stream passes the
+ * launch.
+ */
+tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
+                               const tg_in *W, tg_out *y, const tg_opts *opts,
+                               tg_stream stream);
+
+/*
  * tile_error_norm -- binary64 reductions for the relative Frobenius error of
  * a result against a binary64 reference, on the GPU:
  *   out[0] = sum (C[i] - R[i])^2,  out[1] = sum R[i]^2   over i < n

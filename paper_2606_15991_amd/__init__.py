@@ -106,6 +106,9 @@ def _load():
                              ctypes.c_void_p]
     lib.tile_mul.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                              ctypes.c_void_p]
+    lib.tile_rms_norm_matvec.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
+                                         P(tg_in), P(tg_out), P(tg_opts),
+                                         ctypes.c_void_p]
     lib.tile_rms_norm.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
                                   P(tg_out), P(tg_opts), ctypes.c_void_p]
     lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
@@ -170,7 +173,7 @@ def _load():
         getattr(lib, f).restype = i32
     for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
               "tile_gemm_grouped_prepare", "tile_gemm_grouped",
-              "tile_add", "tile_mul", "tile_rms_norm",
+              "tile_add", "tile_mul", "tile_rms_norm", "tile_rms_norm_matvec",
               "tile_error_norm"):
         getattr(lib, f).restype = i32
     return lib
@@ -326,6 +329,21 @@ def tile_rms_norm(x, w, y, eps=1e-6, bm=0, *, checked=True,
     _raise(lib.tile_rms_norm(make_in(x), make_in(w), float(eps), dy, o,
                              _stream(stream)))
     tile_rms_norm.last_partition = (dy.bm, dy.bn)
+    return y
+
+
+def tile_rms_norm_matvec(x, nw, W, y, eps=1e-6, *, scale_w=None,
+                         checked=True, write_count=None, stream=None):
+    """y = rms_norm(x; nw, eps) . W^T with the normalisation fused into the
+    decode product (x: M x K bf16, M <= 16; nw: K bf16; W stored N x K).
+    Returns y."""
+    if nw.dim() == 1:
+        nw = nw.view(1, -1)
+    dy = make_out(y)
+    o = make_opts(scale_b=scale_w, write_count=write_count, checked=checked)
+    _raise(lib.tile_rms_norm_matvec(make_in(x), make_in(nw), float(eps),
+                                    make_in(W, True), dy, o, _stream(stream)))
+    tile_rms_norm_matvec.last_partition = (dy.bm, dy.bn)
     return y
 
 

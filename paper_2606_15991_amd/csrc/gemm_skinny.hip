@@ -15,6 +15,7 @@
 // and one wavefront stores the sub-tensor: deterministic, no atomics, no
 // workspace.
 #include "tg_device.hpp"
+#include "tg_elementwise.hpp"
 #include "tg_internal.hpp"
 
 namespace tg {
@@ -40,8 +41,17 @@ __device__ __forceinline__ uint4 ld_chunk(const char *row, int k, int K,
     return uint4{0, 0, 0, 0};
 }
 
-template <int WDT, int KS, bool CBF16, int RT>
-__global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
+// NORM: the activation rows are RMS-normalised on the fly (the normalisation
+// step of the decode layer fused into the product): each activation chunk
+// is multiplied by the matching chunk of the normalisation weights nw and
+// rounded to bf16 before the contraction, the lanes accumulate the squares
+// of the raw activations, and every output of row m is multiplied by
+// 1 / sqrt(mean_k x[m, k]^2 + eps).  Every activation element of a row is
+// loaded by exactly one lane of one wavefront of the program, so the
+// program holds the whole row's sum of squares after its reduction.
+template <int WDT, int KS, bool CBF16, int RT, bool NORM>
+__device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
+                                            const void *nw, float eps) {
     // Elements of K covered by one 16-byte weight load per lane group:
     // bf16: 8 per lane, 4 lane groups -> 32;  e4m3: 16 per lane -> 64.
     constexpr int EPL = WDT == TG_BF16 ? 8 : 16;
@@ -49,6 +59,7 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     // K steps per super-step: eight weight loads per lane either way
     constexpr int UNROLL = 8 / RT;
     __shared__ f32x4 part[KS][RT][64];
+    __shared__ float ssq[NORM ? KS : 1][64];
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n0 = blockIdx.x * 16 * RT;
@@ -74,6 +85,8 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     constexpr int WES = WDT == TG_BF16 ? 2 : 1;
     constexpr int XV = WDT == TG_BF16 ? 1 : 2;   // activation chunks per step
     const char *Xc = reinterpret_cast<const char *>(X);
+    const char *NWc = static_cast<const char *>(nw);
+    float ss = 0.f;
     // Wave w takes super-steps w, w + KS, ... of UNROLL K steps each: all
     // UNROLL weight and activation chunks of a super-step are loaded before
     // any is contracted, so every lane has UNROLL weight loads in flight
@@ -85,8 +98,9 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
     // Two register buffers (the wave's next super-step is loaded while the
     // current one is contracted) where the register budget allows: up to
     // 512 threads per program.
-    constexpr int NB = KS <= 8 ? 2 : 1;
+    constexpr int NB = KS <= 8 && !NORM ? 2 : 1;
     uint4 wv[NB][UNROLL][RT], xv[NB][UNROLL][XV];
+    uint4 nv[NORM ? NB : 1][NORM ? UNROLL : 1][NORM ? XV : 1];
     auto load_fast = [&](int s0, int b) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -95,8 +109,11 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
             for (int t = 0; t < RT; ++t)
                 wv[b][u][t] = ld16(W[t] + (int64_t)k * WES);
 #pragma unroll
-            for (int c = 0; c < XV; ++c)
+            for (int c = 0; c < XV; ++c) {
                 xv[b][u][c] = ld16(Xc + (int64_t)(k + 8 * c) * 2);
+                if constexpr (NORM)
+                    nv[b][u][c] = ld16(NWc + (int64_t)(k + 8 * c) * 2);
+            }
         }
     };
     auto load_checked = [&](int s0, int b) {
@@ -110,12 +127,42 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
                                    : uint4{0, 0, 0, 0};
             const bool ok = live && k < g.K;
 #pragma unroll
-            for (int c = 0; c < XV; ++c)
+            for (int c = 0; c < XV; ++c) {
                 xv[b][u][c] = ok ? ld_chunk(Xc, k + 8 * c, g.K, 8, 2)
                                  : uint4{0, 0, 0, 0};
+                if constexpr (NORM)
+                    nv[b][u][c] = ok ? ld_chunk(NWc, k + 8 * c, g.K, 8, 2)
+                                     : uint4{0, 0, 0, 0};
+            }
         }
     };
+    // x * nw rounded to bf16, eight at a time; squares of x into ss
+    auto normed = [&](const uint4 &x, const uint4 &w) -> uint4 {
+        const uint32_t xa[4] = {x.x, x.y, x.z, x.w};
+        const uint32_t wa[4] = {w.x, w.y, w.z, w.w};
+        uint32_t o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float xl = __uint_as_float(xa[q] << 16);
+            const float xh = __uint_as_float(xa[q] & 0xffff0000u);
+            ss += xl * xl;
+            ss += xh * xh;
+            o[q] = (uint32_t)f32_to_bf16_bits(
+                       xl * __uint_as_float(wa[q] << 16)) |
+                   ((uint32_t)f32_to_bf16_bits(
+                        xh * __uint_as_float(wa[q] & 0xffff0000u))
+                    << 16);
+        }
+        return uint4{o[0], o[1], o[2], o[3]};
+    };
     auto contract = [&](int b) {
+        if constexpr (NORM) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u)
+#pragma unroll
+                for (int c = 0; c < XV; ++c)
+                    xv[b][u][c] = normed(xv[b][u][c], nv[b][u][c]);
+        }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
@@ -170,13 +217,24 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
 
 #pragma unroll
     for (int t = 0; t < RT; ++t) part[wave][t][lane] = acc[t];
+    if constexpr (NORM) ssq[wave][lane] = ss;
     __syncthreads();
     if (wave != 0) return;
     // 16 x 16 result layout: lane l, register v holds row 4 * (l / 16) + v
     // (a weight row, i.e. output column) and column l % 16 (an output row).
     const int m = lane & 15;
     if (m >= g.M) return;
-    const float sa = g.scale_a ? g.scale_a[m] : 1.0f;
+    float sa = g.scale_a ? g.scale_a[m] : 1.0f;
+    if constexpr (NORM) {
+        // row m's squares sit in lanes m, m + 16, m + 32, m + 48 of every
+        // wavefront; summed in a fixed order
+        float tot = 0.f;
+#pragma unroll
+        for (int w = 0; w < KS; ++w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) tot += ssq[w][m + 16 * q];
+        sa *= 1.0f / sqrtf(tot / (float)g.K + eps);
+    }
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         f32x4 s = part[0][t][lane];
@@ -200,6 +258,17 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
             }
         }
     }
+}
+
+template <int WDT, int KS, bool CBF16, int RT>
+__global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
+    skinny_body<WDT, KS, CBF16, RT, false>(g, nullptr, 0.f);
+}
+
+template <int WDT, int KS, bool CBF16, int RT>
+__global__ __launch_bounds__(KS * 64) void gemm_skinny_norm_kernel(
+    SkinnyNormArgs a) {
+    skinny_body<WDT, KS, CBF16, RT, true>(a.s, a.norm_w, a.eps);
 }
 
 template <int WDT, int KS, int RT>
@@ -235,7 +304,40 @@ hipError_t launch_bn(int c_bf16, int bn, int ksplit, const SkinnyArgs &a,
     return hipErrorInvalidValue;
 }
 
+template <int WDT, int RT>
+hipError_t launch_norm_rt(int c_bf16, int ksplit, const SkinnyNormArgs &a,
+                          hipStream_t st) {
+    dim3 grid((a.s.N + 16 * RT - 1) / (16 * RT));
+    // the fused normalisation runs with four wavefronts per program
+    if (ksplit != 4) return hipErrorInvalidValue;
+    dim3 block(4 * 64);
+    if (c_bf16)
+        hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, true, RT>), grid,
+                           block, 0, st, a);
+    else
+        hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, false, RT>), grid,
+                           block, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int WDT>
+hipError_t launch_norm_w(int c_bf16, int bn, int ksplit,
+                         const SkinnyNormArgs &a, hipStream_t st) {
+    if (bn == 16) return launch_norm_rt<WDT, 1>(c_bf16, ksplit, a, st);
+    if (bn == 32) return launch_norm_rt<WDT, 2>(c_bf16, ksplit, a, st);
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+hipError_t launch_skinny_norm(int w_dtype, int c_bf16, int bn, int ksplit,
+                              const SkinnyNormArgs &a, hipStream_t st) {
+    if (w_dtype == TG_BF16)
+        return launch_norm_w<TG_BF16>(c_bf16, bn, ksplit, a, st);
+    if (w_dtype == TG_FP8_E4M3)
+        return launch_norm_w<TG_FP8_E4M3>(c_bf16, bn, ksplit, a, st);
+    return hipErrorInvalidValue;
+}
 
 hipError_t launch_skinny(int w_dtype, int c_bf16, int bn, int ksplit,
                          const SkinnyArgs &a, hipStream_t st) {

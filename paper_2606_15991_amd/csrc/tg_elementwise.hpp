@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/tilegemm.h"
+#include "tg_internal.hpp"
 
 namespace tg {
 
@@ -40,5 +41,17 @@ struct NormArgs {
 };
 hipError_t launch_rms_norm(const NormArgs &a, bool vec, int programs,
                            hipStream_t st);
+
+// Decode product with the RMS normalisation of the activation rows fused
+// in: y = diag(1 / sqrt(mean(x^2) + eps)) (x * nw) . W^T (nw: K bf16
+// normalisation weights, one per activation column).  Four wavefronts
+// per program (ksplit 4).
+struct SkinnyNormArgs {
+    SkinnyArgs s;
+    const void *norm_w;
+    float eps;
+};
+hipError_t launch_skinny_norm(int w_dtype, int c_bf16, int bn, int ksplit,
+                              const SkinnyNormArgs &a, hipStream_t st);
 
 }  // namespace tg

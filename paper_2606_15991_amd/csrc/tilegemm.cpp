@@ -941,6 +941,66 @@ tg_status tile_gemm_grouped(void *ws, tg_stream stream) {
     return e == hipSuccess ? TG_OK : hip_fail(e, "grouped kernel launch");
 }
 
+tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
+                               const tg_in *W, tg_out *y, const tg_opts *o,
+                               tg_stream stream) {
+    g_err.clear();
+    tg_status st;
+    if ((st = check_in(nw, "nw")) != TG_OK) return st;
+    if (nw->dtype != TG_BF16 || nw->trans || nw->rows != 1)
+        return fail(TG_E_SHAPE, "nw must be a 1 x K bf16 row");
+    if (!(eps >= 0.0f) || !std::isfinite(eps))
+        return fail(TG_E_ARG, "eps must be finite and >= 0");
+    if (o && (o->precision != TG_PREC_NATIVE || o->config))
+        return fail(TG_E_ARG, "the fused product takes no precision or "
+                              "configuration options");
+    tg_opts oo{};
+    if (o) oo = *o;
+    else oo.checked = 1;
+    tg_config cfg{};
+    cfg.kind = TG_KIND_SKINNY;
+    cfg.ksplit = 4;
+    oo.config = &cfg;
+    Problem p;
+    if ((st = describe(x, W, y, &oo, p)) != TG_OK) return st;
+    if (nw->cols != p.K)
+        return fail(TG_E_SHAPE, "nw has %lld columns, K = %lld",
+                    (long long)nw->cols, (long long)p.K);
+    if (p.K > 0 && ((uintptr_t)nw->data & 15) != 0)
+        return fail(TG_E_SHAPE, "nw must be 16-byte aligned");
+    Launch L;
+    if ((st = choose(p, x, W, y, &oo, L)) != TG_OK) return st;
+    if (oo.checked) {
+        std::vector<int32_t> offs((size_t)L.s.n_prog + 1),
+            ids((size_t)L.s.n_tiles);
+        build_map(L, offs.data(), ids.data());
+        if ((st = check_map(L.s.n_tiles, L.s.n_prog, offs.data(),
+                            ids.data())) != TG_OK)
+            return st;
+        tg_out part = *y;
+        part.bm = L.cfg.bm;
+        part.bn = L.cfg.bn;
+        tg_in ins[3] = {*x, *W, *nw};
+        if ((st = check_alias(ins, 3, &part)) != TG_OK) return st;
+    }
+    y->bm = L.cfg.bm;
+    y->bn = L.cfg.bn;
+    if (p.M == 0 || p.N == 0) return TG_OK;
+    SkinnyNormArgs a;
+    a.s.x = x->data; a.s.w = W->data; a.s.y = y->data;
+    a.s.scale_a = oo.scale_a; a.s.scale_w = oo.scale_b;
+    a.s.wcount = oo.write_count;
+    a.s.ldx = x->ld; a.s.ldw = W->ld; a.s.ldy = y->ld;
+    a.s.M = (int32_t)p.M; a.s.N = (int32_t)p.N; a.s.K = (int32_t)p.K;
+    a.s.bn = L.cfg.bn;
+    a.norm_w = nw->data;
+    a.eps = eps;
+    hipError_t e = launch_skinny_norm(p.b_dt, p.c_bf16, L.cfg.bn,
+                                      L.cfg.ksplit, a,
+                                      static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? TG_OK : hip_fail(e, "fused decode launch");
+}
+
 namespace {
 tg_status tile_elementwise(bool mul, const tg_in *x, const tg_in *y,
                            tg_out *z, const tg_opts *opts, tg_stream stream) {

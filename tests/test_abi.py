@@ -286,6 +286,29 @@ def test_tile_rms_norm_rejects_before_enqueue():
     assert err(e, w, torch.empty((0, 64), dtype=bf)) == tg.TG_OK
 
 
+def test_tile_rms_norm_matvec_rejects_before_enqueue():
+    bf = torch.bfloat16
+    x, nw = torch.empty((2, 64), dtype=bf), torch.empty((1, 64), dtype=bf)
+    W, y = torch.empty((32, 64), dtype=bf), torch.empty((2, 32))
+
+    def err(x, nw, W, y, eps=1e-6, opts=None):
+        return tg.lib.tile_rms_norm_matvec(tg.make_in(x), tg.make_in(nw), eps,
+                                           tg.make_in(W, True),
+                                           tg.make_out(y), opts, None)
+    assert err(x, nw[:, :32], W, y) == tg.TG_E_SHAPE
+    assert err(x, nw.float(), W, y) == tg.TG_E_SHAPE
+    assert err(x, nw, W, y, eps=-1.0) == tg.TG_E_ARG
+    assert err(x, nw, W, y, opts=tg.make_opts("bf16x3")) == tg.TG_E_ARG
+    assert err(x, nw, W, torch.empty((2, 31))) == tg.TG_E_SHAPE
+    x17 = torch.empty((17, 64), dtype=bf)
+    assert err(x17, nw, W, torch.empty((17, 32))) == tg.TG_E_UNSUPPORTED
+    # the output may not overlap the normalisation weights
+    big = torch.empty(4096, dtype=torch.uint8)
+    nw_al = big[:128].view(bf).view(1, 64)
+    y_al = big.view(torch.float32)[:64].view(2, 32)
+    assert err(x, nw_al, W, y_al) == tg.TG_E_ALIAS
+
+
 def test_status_strings():
     assert tg.status_str(tg.TG_E_OVERLAP) == "TG_E_OVERLAP"
     assert tg.status_str(99) == "unknown status"

@@ -83,11 +83,54 @@ def test_rms_norm_rejects_bad_arguments():
                                 1e-6, dy, None, None) == tg.TG_E_ARG
 
 
+@pytest.mark.parametrize("M,N,K", [(1, 5120, 5120), (8, 300, 1008),
+                                   (16, 64, 528), (3, 4096, 16384)])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+@pytest.mark.parametrize("out", [torch.float32, torch.bfloat16])
+def test_fused_norm_matvec_matches_oracle(M, N, K, wdt, out):
+    note("fused norm matvec", M, N, K, wdt, out)
+    x = synth.to_bf16(synth.normal((M, K), 31, std=2.0))
+    nw = (1.0 + synth.normal((K,), 32, std=0.1)).to(torch.bfloat16)
+    w = synth.normal((N, K), 33, std=0.02)
+    if wdt == "bf16":
+        W, sw = synth.to_bf16(w), None
+    else:
+        W, sw = synth.quant_e4m3_rows(w)
+    y = torch.full((M, N), float("nan"), dtype=out, device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    tg.tile_rms_norm_matvec(x.to(DEV), nw.to(DEV), W.to(DEV), y, 1e-6,
+                            scale_w=None if sw is None else sw.to(DEV),
+                            write_count=wc)
+    torch.cuda.synchronize()
+    xn = oracle.rms_norm(exact64(x), exact64(nw), 1e-6)
+    R = oracle.gemm(xn, exact64(W), b_nk=True,
+                    sb=None if sw is None else exact64(sw))
+    assert rel_err(y, R) < 4e-3
+    assert int(wc.min()) == 1 and int(wc.max()) == 1
+
+
+def test_fused_norm_matvec_rejects_bad_arguments():
+    note("fused norm matvec argument errors")
+    x = torch.ones((1, 64), dtype=torch.bfloat16, device=DEV)
+    nw = torch.ones((64,), dtype=torch.bfloat16, device=DEV)
+    W = torch.ones((32, 64), dtype=torch.bfloat16, device=DEV)
+    y = torch.empty((1, 32), device=DEV)
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm_matvec(x, nw[:32], W, y)
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm_matvec(x, nw, W, y, eps=-1.0)
+    with pytest.raises(tg.TileGemmError):
+        tg.tile_rms_norm_matvec(torch.ones((17, 64), dtype=torch.bfloat16,
+                                           device=DEV), nw, W,
+                                torch.empty((17, 32), device=DEV))
+
+
 class Layer:
     """One decode layer: norm = rms_norm(input), q = norm . Wq^T,
     residual = input + q, all bf16 buffers allocated up front."""
 
-    def __init__(self, d, seed):
+    def __init__(self, d, seed, fused=False):
+        self.fused = fused
         self.x = synth.to_bf16(synth.normal((1, d), seed)).to(DEV)
         self.nw = (1.0 + synth.normal((d,), seed + 1, std=0.1)).to(
             torch.bfloat16).to(DEV)
@@ -99,8 +142,14 @@ class Layer:
         self.eps = 1e-6
 
     def run(self, stream=None):
-        tg.tile_rms_norm(self.x, self.nw, self.norm, self.eps, stream=stream)
-        tg.tile_gemm(self.norm, self.W, self.q, b_trans=True, stream=stream)
+        if self.fused:
+            tg.tile_rms_norm_matvec(self.x, self.nw, self.W, self.q,
+                                    self.eps, stream=stream)
+        else:
+            tg.tile_rms_norm(self.x, self.nw, self.norm, self.eps,
+                             stream=stream)
+            tg.tile_gemm(self.norm, self.W, self.q, b_trans=True,
+                         stream=stream)
         tg.tile_add(self.x, self.q, self.res, stream=stream)
 
     def oracle(self):
@@ -113,10 +162,11 @@ class Layer:
         return oracle.decode_bf16(oracle.add_bf16(xb, q))
 
 
+@pytest.mark.parametrize("fused", [False, True])
 @pytest.mark.parametrize("d", [5120, 1000])
-def test_decode_layer_eager_and_graph_replays(d):
-    note("decode layer", d)
-    L = Layer(d, 21)
+def test_decode_layer_eager_and_graph_replays(d, fused):
+    note("decode layer", d, "fused" if fused else "three kernels")
+    L = Layer(d, 21, fused)
     L.run()
     torch.cuda.synchronize()
     eager = L.res.clone()
