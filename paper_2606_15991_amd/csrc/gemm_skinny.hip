@@ -98,7 +98,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     // Two register buffers (the wave's next super-step is loaded while the
     // current one is contracted) where the register budget allows: up to
     // 512 threads per program.
-    constexpr int NB = KS <= 8 && !NORM ? 2 : 1;
+    constexpr int NB = KS <= 8 ? 2 : 1;
     uint4 wv[NB][UNROLL][RT], xv[NB][UNROLL][XV];
     uint4 nv[NORM ? NB : 1][NORM ? UNROLL : 1][NORM ? XV : 1];
     auto load_fast = [&](int s0, int b) {
@@ -136,8 +136,11 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             }
         }
     };
-    // x * nw rounded to bf16, eight at a time; squares of x into ss
+    // x * nw rounded to bf16 (round to nearest even, by the packed
+    // hardware conversion), eight at a time; squares of x into ss
     auto normed = [&](const uint4 &x, const uint4 &w) -> uint4 {
+        typedef float f32x2_t __attribute__((ext_vector_type(2)));
+        typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
         const uint32_t xa[4] = {x.x, x.y, x.z, x.w};
         const uint32_t wa[4] = {w.x, w.y, w.z, w.w};
         uint32_t o[4];
@@ -147,11 +150,10 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             const float xh = __uint_as_float(xa[q] & 0xffff0000u);
             ss += xl * xl;
             ss += xh * xh;
-            o[q] = (uint32_t)f32_to_bf16_bits(
-                       xl * __uint_as_float(wa[q] << 16)) |
-                   ((uint32_t)f32_to_bf16_bits(
-                        xh * __uint_as_float(wa[q] & 0xffff0000u))
-                    << 16);
+            const f32x2_t p = {xl * __uint_as_float(wa[q] << 16),
+                               xh * __uint_as_float(wa[q] & 0xffff0000u)};
+            o[q] = __builtin_bit_cast(
+                uint32_t, __builtin_convertvector(p, bf16x2_t));
         }
         return uint4{o[0], o[1], o[2], o[3]};
     };
