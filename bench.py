@@ -122,6 +122,30 @@ def oracle_rows(A, B, rows, b_nk=False, sa=None, sb=None, target_s=10.0):
     return np.asarray(done), np.concatenate(R, axis=0), secs
 
 
+def clock_sample():
+    """Current shader (SCLK) and memory (MCLK) clocks in MHz from the
+    driver's sysfs DPM tables (the level marked '*'), or None where the
+    files are not readable."""
+    import glob
+    out = {}
+    for name, key in (("pp_dpm_sclk", "sclk_mhz"), ("pp_dpm_mclk",
+                                                    "mclk_mhz")):
+        for f in sorted(glob.glob(f"/sys/class/drm/card*/device/{name}")):
+            try:
+                with open(f) as fh:
+                    for line in fh:
+                        if "*" in line:
+                            mhz = "".join(ch for ch in line.split(":")[-1]
+                                          if ch.isdigit())
+                            if mhz:
+                                out[key] = int(mhz)
+            except OSError:
+                continue
+            if key in out:
+                break
+    return out or None
+
+
 def bench_bf16_main(args, tg):
     M = N = K = 8192
     log("bf16 8192^3: generating inputs")
@@ -133,33 +157,69 @@ def bench_bf16_main(args, tg):
     def step():
         tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True)
 
-    log("bf16 8192^3: timing")
+    # clock settling: back-to-back launches for --settle-ms of wall time
+    # before the warm-up (after start-up the power manager first lowers the
+    # clock; launch durations settle after about 50 launches)
+    settle = 0
+    t0 = time.perf_counter()
+    while (time.perf_counter() - t0) * 1e3 < args.settle_ms:
+        for _ in range(10):
+            step()
+        settle += 10
+        torch.cuda.synchronize()
+    log(f"bf16 8192^3: {settle} settling launches, timing")
     ms = timed(step, args.steps, args.warmup)
     flops = 2.0 * M * N * K
     tflops = flops / (ms * 1e-3) / 1e12
-    # unchecked twin: same kernel, partition check skipped on the host
-    ms_unchecked = timed(lambda: tg.tile_gemm(Ad, Bd, C, 256, 256,
-                                              b_trans=True, checked=False),
-                         max(args.steps // 2, 5), 2)
-    # per-launch durations (events between back-to-back launches) for the
-    # spread of the same workload
+    # the safe / unsafe twins of Sec. 5.1: the checked launch (ownership
+    # rules run on the host) against the unchecked one, interleaved
+    # A B B A ... in the same warm state; device time of each launch from
+    # events, host time of each call from the wall clock
     s = torch.cuda.current_stream()
+    dev_ms = {True: [], False: []}
+    host_us = {True: [], False: []}
+    pairs = 20
+    for i in range(pairs):
+        for checked in ((True, False) if i % 2 == 0 else (False, True)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            h0 = time.perf_counter()
+            tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True, checked=checked)
+            host_us[checked].append((time.perf_counter() - h0) * 1e6)
+            e1.record(s)
+            e1.synchronize()
+            dev_ms[checked].append(e0.elapsed_time(e1))
+    twins = {"pairs": pairs, "order": "ABBA interleaved",
+             "checked_ms_median": float(np.median(dev_ms[True])),
+             "unchecked_ms_median": float(np.median(dev_ms[False])),
+             "checked_over_unchecked": float(np.median(dev_ms[True]) /
+                                             np.median(dev_ms[False])),
+             "checked_host_us_median": float(np.median(host_us[True])),
+             "unchecked_host_us_median": float(np.median(host_us[False]))}
+    # per-launch durations (events between back-to-back launches) for the
+    # spread of the same workload, with the clocks sampled while they run
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(31)]
     ev[0].record(s)
     for i in range(30):
         step()
         ev[i + 1].record(s)
+    clocks = [clock_sample() for _ in range(5)]
     torch.cuda.synchronize()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(30)])
     spread = {"launches": 30, "p25_ms": float(np.percentile(per, 25)),
               "median_ms": float(np.median(per)),
               "p75_ms": float(np.percentile(per, 75))}
+    clocks = [c for c in clocks if c]
+    clock = {"source": "sysfs pp_dpm_sclk / pp_dpm_mclk, sampled during "
+                       "the 30 launches", "samples": clocks} if clocks else \
+        {"source": "unavailable (no readable DPM table)", "samples": []}
     step()
     torch.cuda.synchronize()
     Cc = C.cpu().numpy()
     res = {"M": M, "N": N, "K": K, "ms": ms, "tflops": tflops,
-           "ms_unchecked": ms_unchecked, "spread": spread, "A": A, "Bt": Bt,
-           "C": Cc}
+           "twins": twins, "spread": spread, "clock": clock,
+           "settle_launches": settle, "A": A, "Bt": Bt, "C": Cc}
     return res
 
 
@@ -234,15 +294,22 @@ def bench_fp8(args, tg, n=8192):
             PEAK_TFLOPS["fp8"]}
 
 
-def bench_f32_and_split(args, tg, n=8192):
+def bench_f32_and_split(args, tg, n=8192, sample_rows=8):
+    """Plain f32 and BF16x3 / BF16x6 at n^3 (f32 N(0,1) operands).  Keeps a
+    seeded sample of output rows of each for the oracle's error check in
+    the CPU leg."""
     log(f"f32 / split {n}^3")
-    A = synth.normal((n, n), 2).cuda()
-    B = synth.normal((n, n), 202).cuda()
+    A32 = synth.normal((n, n), 2)
+    B32 = synth.normal((n, n), 202)
+    A, B = A32.cuda(), B32.cuda()
     C = torch.empty((n, n), device="cuda")
-    out = {}
+    rows = np.sort(np.random.default_rng(5).permutation(n)[:sample_rows])
+    rows_t = torch.from_numpy(rows).cuda()
+    out, kept = {}, {}
     ms = timed(lambda: tg.tile_gemm(A, B, C, 128, 128), 3, 1)
     out["f32_ms"] = ms
     out["f32_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    kept["f32"] = C[rows_t].cpu().numpy()
     for prec in ("bf16x3", "bf16x6"):
         ws = torch.empty(tg.tile_gemm_workspace_size(A, B, C,
                                                      precision=prec),
@@ -251,8 +318,25 @@ def bench_f32_and_split(args, tg, n=8192):
                                         workspace=ws), 3, 1)
         out[prec + "_ms"] = ms
         out[prec + "_eff_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+        kept[prec] = C[rows_t].cpu().numpy()
         del ws
+    out["_sample"] = {"A": A32, "B": B32, "rows": rows, "C": kept}
     return out
+
+
+def cpu_leg_split_errors(sample):
+    """Relative Frobenius error of the f32, BF16x3 and BF16x6 results on
+    their sampled rows against the oracle's binary64 product of the f32
+    inputs (part of the CPU leg: the oracle runs here only)."""
+    import oracle
+    rows = sample["rows"]
+    a = sample["A"].numpy().astype(np.float64)[rows]
+    b = sample["B"].numpy().astype(np.float64)
+    R = oracle.gemm(a, b)
+    errs = {k + "_err_rel_fro": oracle.rel_fro(v.astype(np.float64), R)
+            for k, v in sample["C"].items()}
+    errs["split_err_rows"] = int(len(rows))
+    return errs
 
 
 def graph_ms(calls, reps=20, warmup=3):
@@ -565,6 +649,9 @@ def main():
     ap.add_argument("--quick", action="store_true",
                     help="headline workload only")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--settle-ms", type=float, default=1000.0,
+                    help="wall time of back-to-back headline launches "
+                         "before the warm-up (clock settling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--decode", action="store_true",
@@ -620,8 +707,9 @@ def main():
         return
 
     res = bench_bf16_main(args, tg)
-    extra = {"ms_unchecked_launch": res["ms_unchecked"],
-             "launch_spread": res["spread"]}
+    extra = {"checked_vs_unchecked": res["twins"],
+             "launch_spread": res["spread"],
+             "settle_launches": res["settle_launches"]}
     if not args.quick:
         extra["fp8_8192"] = bench_fp8(args, tg)
         extra.update(bench_f32_and_split(args, tg))
@@ -641,6 +729,8 @@ def main():
             picker.main([])
         extra["picker"] = json.loads(buf.getvalue().strip().splitlines()[-1])
     err, cpu, nrows = cpu_baseline_and_err(res, args.cpu_seconds)
+    if "_sample" in extra:
+        extra.update(cpu_leg_split_errors(extra.pop("_sample")))
     tflops = res["tflops"]
     line = {
         "metric": METRIC,
@@ -664,6 +754,7 @@ def main():
                      "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(tflops / PEAK_TFLOPS["bf16"], 4),
                      "traffic": traffic_from_profile()},
+        "clock": res["clock"],
         "err_rel_fro": err,
         "err_rows": nrows,
         "cpu_baseline": cpu,

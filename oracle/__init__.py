@@ -246,3 +246,21 @@ def partition_paint(M, N, bm, bn, prog_offsets=None, prog_tiles=None):
 
 def ranges_intersect(a: int, na: int, b: int, nb: int) -> bool:
     return bool(_load().oracle_ranges_intersect(a, na, b, nb))
+
+
+def rms_norm_matvec(x, nw, W, eps: float, sw=None) -> np.ndarray:
+    """The decode layer's normalisation fused into its product (Sec. 3.2,
+    graph-scope listing: rms_norm, then the matvec), binary64:
+
+        y[m, n] = s_m * sum_k round_bf16(x[m, k] * nw[k]) * W[n, k] * sw[n]
+        s_m     = 1 / sqrt(mean_k x[m, k]^2 + eps)
+
+    W is stored N x K.  Reading: the weighted activation x * nw is held at
+    the width of the stored normalised buffer of the unfused chain (bf16,
+    round to nearest even) before the contraction, and the row scale s_m
+    multiplies the finished sum; sw (N,) or None are per-output scales."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    nw = np.asarray(nw, dtype=np.float64).reshape(-1)
+    xw = decode_bf16(round_bf16(x * nw))
+    s = 1.0 / np.sqrt(np.mean(x * x, axis=1) + float(eps))
+    return gemm(xw, W, b_nk=True, sa=s, sb=sw)

@@ -276,29 +276,129 @@ def test_split_precision(b_trans):
 
 # ----------------------------------------------------- full-size, sampled
 
-def test_bf16_8192_sampled_against_oracle():
-    """The benchmarked workload, in the benchmarked launch configuration:
-    8192^3 bf16 N(0,1), 256 x 256 partition; 2048 sampled outputs."""
+@pytest.mark.parametrize("b_trans", [False, True])
+def test_split_precision_8192_sampled(b_trans):
+    """BF16x6 and BF16x3 at 8192^3 (f32 N(0,1) operands, the benchmarked
+    split-precision workload): sampled whole rows against the oracle's
+    exact product of the f32 inputs.  x6 meets 2e-6; x3 stays within 6e-6
+    (two bf16 planes keep about 16 significand bits)."""
+    import oracle
     M = N = K = 8192
-    note("bf16 8192^3 sampled")
-    A = synth.to_bf16(synth.normal((M, K), 2))
-    B = synth.to_bf16(synth.normal((K, N), 202))
+    A = synth.normal((M, K), 2)
+    B = synth.normal((N, K) if b_trans else (K, N), 202)
+    Ad, Bd = dev(A), dev(B)
+    rows = np.sort(np.random.default_rng(5).permutation(M)[:8])
+    R = oracle_rows(A, B, rows, b_trans)
     C = torch.empty((M, N), device=DEV)
-    tg.tile_gemm(dev(A), dev(B), C, 256, 256)
+    errs = {}
+    for prec, bar in (("bf16x6", 2e-6), ("bf16x3", 6e-6)):
+        note("split 8192^3", prec, "b_trans", b_trans)
+        C.fill_(float("nan"))
+        tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=b_trans, precision=prec)
+        torch.cuda.synchronize()
+        errs[prec] = oracle.rel_fro(
+            C.cpu().numpy()[rows].astype(np.float64), R)
+        note("split 8192^3 %s err %.3g" % (prec, errs[prec]))
+        assert errs[prec] <= bar, (prec, errs[prec])
+    assert errs["bf16x6"] < errs["bf16x3"]
+
+
+def test_grouped_c4_batch_graph_replayed():
+    """The 64-problem grouped workload (seed 4: M ~ U{1..2048}, N and K
+    ~ 128 U{8..64}, N(0,1) bf16 operands, binary32 outputs) in one
+    persistent launch: every problem's sampled rows (its last row among
+    them) against the oracle, then the launch captured in a HIP graph and
+    replayed three times, each replay bit for bit equal to the eager
+    launch."""
+    import oracle
+    shapes = synth.grouped_shapes(4, 64)
+    note("grouped c4 batch: generating 64 problems")
+    As = [synth.to_bf16(synth.normal((m, k), 1000 + i))
+          for i, (m, n, k) in enumerate(shapes)]
+    Bs = [synth.to_bf16(synth.normal((k, n), 2000 + i))
+          for i, (m, n, k) in enumerate(shapes)]
+    Ad = [dev(a) for a in As]
+    Bd = [dev(b) for b in Bs]
+    Cs = [torch.full((m, n), float("nan"), device=DEV) for m, n, k in shapes]
+    note("grouped c4 batch: prepare + launch")
+    launch = tg.tile_gemm_grouped_prepare(Ad, Bd, Cs)
+    tg.tile_gemm_grouped(launch)
     torch.cuda.synchronize()
+    eager = [c.clone() for c in Cs]
+    rng = np.random.default_rng(4)
+    for i, (m, n, k) in enumerate(shapes):
+        rows = np.unique(np.concatenate(
+            [rng.integers(0, m, 2), [m - 1]])).astype(np.int64)
+        R = oracle_rows(As[i], Bs[i], rows, False)
+        got = eager[i].cpu().numpy()[rows].astype(np.float64)
+        err = oracle.rel_fro(got, R)
+        assert err <= 1e-5, (i, (m, n, k), err)
+    note("grouped c4 batch: graph replays")
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tg.tile_gemm_grouped(launch, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for c in Cs:
+            c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (c, e) in enumerate(zip(Cs, eager)):
+            assert torch.equal(c, e), (rep, i)
+
+
+@pytest.mark.parametrize("b_trans", [True, False])
+def test_bf16_8192_sampled_against_oracle(b_trans):
+    """8192^3 bf16 N(0,1), 256 x 256 partition.  b_trans=True is the
+    benchmarked launch exactly (B held as its N x K transpose, the default
+    configuration tile_gemm picks for it: the cross-tile ring over 128 K
+    tiles, several owned sub-tensors per program); b_trans=False stores B
+    K x N.  Sampled entries (every sub-tensor's corners among them) and
+    whole sampled rows against the oracle, and one store per element."""
+    import oracle
+    M = N = K = 8192
+    note("bf16 8192^3 sampled, b_trans", b_trans)
+    A = synth.to_bf16(synth.normal((M, K), 2))
+    B = synth.to_bf16(synth.normal((N, K) if b_trans else (K, N), 202))
+    Ad, Bd = dev(A), dev(B)
+    C = torch.empty((M, N), device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    if b_trans:
+        cfg, n_prog, _, _ = tg.tile_gemm_plan(Ad, Bd, C, 256, 256,
+                                              b_trans=True, want_map=False)
+        assert cfg["sched"] == tg.TG_SCHED_CROSS, cfg
+        assert n_prog < (M // 256) * (N // 256), n_prog
+    # the benchmarked call (unchecked twin included), then the counted one
+    tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=b_trans)
+    torch.cuda.synchronize()
+    Cb = C.clone()
+    tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=b_trans, checked=False)
+    tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=b_trans, write_count=wc)
+    torch.cuda.synchronize()
+    assert torch.equal(C, Cb)
+    assert int(wc.min()) == 1 and int(wc.max()) == 1
+    del wc
     rng = np.random.default_rng(2)
     ii = rng.integers(0, M, 2048)
     jj = rng.integers(0, N, 2048)
-    # every 256 x 256 sub-tensor's corners as well
+    # every 256 x 256 sub-tensor's four corners
     corners = np.arange(0, M, 256)
-    ii = np.concatenate([ii, np.repeat(corners, 32), np.repeat(corners + 255,
-                                                               32)])
-    jj = np.concatenate([jj, np.tile(corners, 32), np.tile(corners + 255, 32)])
-    R = reference_entries(A, B, ii, jj)
-    got = C.cpu().numpy().astype(np.float64)[ii, jj]
-    import oracle
-    assert oracle.rel_fro(got, R) <= 1e-5
+    cm, cn = np.meshgrid(corners, corners, indexing="ij")
+    for dm in (0, 255):
+        for dn in (0, 255):
+            ii = np.concatenate([ii, (cm + dm).ravel()])
+            jj = np.concatenate([jj, (cn + dn).ravel()])
+    R = reference_entries(A, B, ii, jj, b_trans)
+    Cc = Cb.cpu().numpy().astype(np.float64)
+    got = Cc[ii, jj]
     assert np.all(np.isfinite(got))
+    assert oracle.rel_fro(got, R) <= 1e-5
+    rows = np.sort(rng.permutation(M)[:6])
+    Rr = oracle_rows(A, B, rows, b_trans)
+    assert oracle.rel_fro(Cc[rows], Rr) <= 1e-5
 
 
 @pytest.mark.parametrize("N,K", synth.DECODE_SHAPES)
@@ -653,7 +753,7 @@ def test_every_bf16_variant_bit_exact(M, N, K, b_trans):
 
 @pytest.mark.parametrize("b_trans", [False, True])
 @pytest.mark.parametrize("M,N,K", [(300, 264, 136), (520, 600, 328),
-                                   (4352, 4352, 72)])
+                                   (4352, 4352, 72), (4352, 4352, 2048)])
 def test_every_bf16_variant_normal_inputs(M, N, K, b_trans):
     """N(0,1) bf16 operands: every tiled configuration within the binary32
     bar."""

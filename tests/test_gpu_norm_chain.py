@@ -8,6 +8,10 @@ Tolerances:
   * rms_norm, bf16 output: relative 2^-8 + 1e-5 per element (one bf16
     rounding of the binary32 value: bf16 keeps 8 significant bits, so its
     unit roundoff is 2^-8);
+  * the fused normalisation + product: relative Frobenius 1e-5 (binary32
+    output) against the oracle's fused definition, which holds x * nw in
+    bf16 as the kernel does, 4e-3 for bf16 output and against the plain
+    chain; small-integer cases bit-exact;
   * the layer (bf16 buffers): relative Frobenius 4e-3 against the oracle's
     chain, which rounds each intermediate buffer to bf16 as the layer
     stores it (bf16 unit roundoff 2^-8).
@@ -102,10 +106,53 @@ def test_fused_norm_matvec_matches_oracle(M, N, K, wdt, out):
                             scale_w=None if sw is None else sw.to(DEV),
                             write_count=wc)
     torch.cuda.synchronize()
+    sw64 = None if sw is None else exact64(sw)
+    # the fused definition: x * nw held in bf16, row scale on the sum
+    R = oracle.rms_norm_matvec(exact64(x), exact64(nw), exact64(W), 1e-6,
+                               sw64)
+    err = rel_err(y, R)
+    note("fused err %.3g" % err)
+    assert err <= (1e-5 if out == torch.float32 else 4e-3), err
+    # and the plain chain without the intermediate rounding, within the
+    # bf16 rounding of the weighted activations
     xn = oracle.rms_norm(exact64(x), exact64(nw), 1e-6)
-    R = oracle.gemm(xn, exact64(W), b_nk=True,
-                    sb=None if sw is None else exact64(sw))
-    assert rel_err(y, R) < 4e-3
+    Rc = oracle.gemm(xn, exact64(W), b_nk=True, sb=sw64)
+    assert rel_err(y, Rc) < 4e-3
+    assert int(wc.min()) == 1 and int(wc.max()) == 1
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 5120, 5120), (4, 300, 1008),
+                                   (16, 64, 4096)])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+@pytest.mark.parametrize("out", [torch.float32, torch.bfloat16])
+def test_fused_norm_matvec_small_integers_bit_exact(M, N, K, wdt, out):
+    """Activation rows of +-2^j (j = m mod 4; eps 0, so the row scale is
+    2^-j exactly), power-of-two normalisation weights and small-integer
+    weights: every x * nw is a bf16 value, every partial sum an integer
+    below 2^24, so the result is exact (bf16 output: one rounding of it)."""
+    note("fused norm matvec exact", M, N, K, wdt, out)
+    g = torch.Generator().manual_seed(34)
+    sign = torch.randint(0, 2, (M, K), generator=g).float() * 2 - 1
+    j = (torch.arange(M) % 4).float()[:, None]
+    x = (sign * 2.0 ** j).to(torch.bfloat16)
+    nw = (2.0 ** torch.randint(-1, 3, (K,), generator=g).float()).to(
+        torch.bfloat16)
+    Wi = synth.small_int((N, K), 35)
+    W = Wi.to(torch.bfloat16) if wdt == "bf16" else Wi.to(
+        torch.float8_e4m3fn)
+    sw = None if wdt == "bf16" else 2.0 ** torch.randint(
+        -2, 3, (N,), generator=g).float()
+    y = torch.full((M, N), float("nan"), dtype=out, device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    tg.tile_rms_norm_matvec(x.to(DEV), nw.to(DEV), W.to(DEV), y, 0.0,
+                            scale_w=None if sw is None else sw.to(DEV),
+                            write_count=wc)
+    torch.cuda.synchronize()
+    R = oracle.rms_norm_matvec(exact64(x), exact64(nw), exact64(W), 0.0,
+                               None if sw is None else exact64(sw))
+    want = R if out == torch.float32 else oracle.decode_bf16(
+        oracle.round_bf16(R))
+    assert np.array_equal(exact64(y), want)
     assert int(wc.min()) == 1 and int(wc.max()) == 1
 
 

@@ -104,3 +104,82 @@ def test_planted_missing_relu_mask_fails_the_pin(monkeypatch):
                                for g, b in grads])
     fd = fd_grad(lambda q: mlp.loss(q, X, y, *arch), p)
     assert np.max(np.abs(bad_grad(p, X, y, *arch) - fd)) > 1e-4
+
+
+def _adam_run(p, gs, m, v, t0, **hp):
+    """Successive Adam steps t0, t0 + 1, ... with the gradients gs."""
+    for i, g in enumerate(gs):
+        p, m, v = mlp.adam(p, g, m, v, t0 + i, **hp)
+    return p, m, v
+
+
+def test_adam_constant_gradient_closed_form():
+    """From zero moments a constant gradient g gives m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so both bias-corrected moments equal g and g^2 at
+    every step and each step moves p by -lr g / (|g| + eps)."""
+    rng = np.random.default_rng(6)
+    p0 = rng.normal(size=16)
+    g = rng.normal(size=16)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    p, m, v = p0, np.zeros(16), np.zeros(16)
+    for t in range(1, 13):
+        p, m, v = mlp.adam(p, g, m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        assert np.allclose(m, (1 - b1 ** t) * g, rtol=1e-13, atol=0)
+        assert np.allclose(v, (1 - b2 ** t) * g * g, rtol=1e-12, atol=0)
+        assert np.allclose(p, p0 - t * lr * g / (np.abs(g) + eps),
+                           rtol=1e-12, atol=1e-15)
+
+
+def test_adam_zero_gradient_decays_moments_geometrically():
+    """With g = 0 the moments decay as m_t = b1^n m_0, v_t = b2^n v_0 after
+    n steps, and each step moves p against the bias-corrected ratio."""
+    rng = np.random.default_rng(7)
+    p0 = rng.normal(size=12)
+    m0 = rng.normal(size=12)
+    v0 = rng.uniform(0.5, 2.0, 12)
+    lr, b1, b2, eps = 1e-3, 0.8, 0.99, 1e-8
+    n, t0 = 9, 4
+    p, m, v = _adam_run(p0, [np.zeros(12)] * n, m0, v0, t0, lr=lr, b1=b1,
+                        b2=b2, eps=eps)
+    assert np.allclose(m, b1 ** n * m0, rtol=1e-13, atol=0)
+    assert np.allclose(v, b2 ** n * v0, rtol=1e-13, atol=0)
+    # p moved by sum over steps j = 1..n of lr * mhat_j / (sqrt(vhat_j) + eps)
+    # with mhat_j = b1^j m0 / (1 - b1^(t0+j-1)), likewise vhat_j
+    step = np.zeros(12)
+    for j in range(1, n + 1):
+        t = t0 + j - 1
+        mh = b1 ** j * m0 / (1 - b1 ** t)
+        vh = b2 ** j * v0 / (1 - b2 ** t)
+        step += lr * mh / (np.sqrt(vh) + eps)
+    assert np.allclose(p, p0 - step, rtol=1e-12, atol=1e-15)
+
+
+def _adam_no_decay(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    m = (1 - b1) * g                      # planted: b1 * m dropped
+    v = (1 - b2) * g * g                  # planted: b2 * v dropped
+    return (p - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps),
+            m, v)
+
+
+def _adam_wrong_correction(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999,
+                           eps=1e-8):
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1)                     # planted: b1 in place of b1**t
+    vh = v / (1 - b2)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+@pytest.mark.parametrize("bad", [_adam_no_decay, _adam_wrong_correction])
+def test_planted_adam_mistakes_fail_the_pins(monkeypatch, bad):
+    """Each planted mistake (on the CPU, in a copy of the update) breaks the
+    constant-gradient or the zero-gradient closed form."""
+    monkeypatch.setattr(mlp, "adam", bad)
+    failed = 0
+    for pin in (test_adam_constant_gradient_closed_form,
+                test_adam_zero_gradient_decays_moments_geometrically):
+        try:
+            pin()
+        except AssertionError:
+            failed += 1
+    assert failed >= 1

@@ -94,3 +94,63 @@ def test_planted_norm_mistakes_fail_a_pin(kind):
         np.allclose(f(x[2:3], w, 0.3), f(x, w, 0.3)[2:3]),
     ]
     assert not all(checks)
+
+
+# ------------------------------------------- fused normalisation + product
+
+def test_fused_norm_matvec_equals_chain_when_rounding_is_exact():
+    """With power-of-two normalisation weights and bf16 activations every
+    x * nw is a bf16 value, so the fused definition reduces to the plain
+    chain rms_norm(x, nw) . W^T (row scale factored out of the sum)."""
+    rng = np.random.default_rng(11)
+    M, K, N = 3, 40, 7
+    x = oracle.decode_bf16(oracle.round_bf16(rng.standard_normal((M, K))))
+    nw = 2.0 ** rng.integers(-2, 3, K)
+    W = rng.standard_normal((N, K))
+    sw = rng.uniform(0.5, 2.0, N)
+    for eps in (0.0, 1e-3):
+        got = oracle.rms_norm_matvec(x, nw, W, eps, sw)
+        want = oracle.rms_norm(x, nw, eps) @ W.T * sw
+        assert np.allclose(got, want, rtol=1e-13, atol=1e-15)
+
+
+def test_fused_norm_matvec_small_integers_exact():
+    """Rows of +-2^j (mean square 4^j, eps 0: row scale 2^-j exactly),
+    power-of-two weights and small-integer W: an exact integer sum halved
+    j times."""
+    rng = np.random.default_rng(12)
+    M, K, N = 4, 64, 5
+    sign = np.where(rng.integers(0, 2, (M, K)) == 1, 1.0, -1.0)
+    j = np.arange(M)[:, None]
+    x = sign * 2.0 ** j
+    nw = 2.0 ** rng.integers(-1, 3, K)
+    W = rng.integers(-4, 5, (N, K)).astype(np.float64)
+    got = oracle.rms_norm_matvec(x, nw, W, 0.0)
+    want = (sign * nw) @ W.T           # x * nw / 2^j = sign * nw
+    assert np.array_equal(got, want)
+
+
+def test_fused_norm_matvec_worked_rounding_example():
+    """K = 2, x = (1 + 2^-7, 1 + 2^-7), nw = (1 + 2^-7, 1), W = (1, 1):
+    x0 nw0 = 1 + 2^-6 + 2^-14 rounds to the bf16 value 1 + 2^-6 (2^-14 is
+    below half a bf16 unit at 1, 2^-8), x1 nw1 = 1 + 2^-7 is exact, and the
+    mean square is (1 + 2^-7)^2, so y = (2 + 3 2^-7) / (1 + 2^-7)."""
+    a = 1.0 + 2.0 ** -7
+    got = oracle.rms_norm_matvec([[a, a]], [a, 1.0], [[1.0, 1.0]], 0.0)
+    assert got[0, 0] == pytest.approx((2.0 + 3 * 2.0 ** -7) / a, rel=1e-15)
+    # without the intermediate rounding the 2^-14 term would survive
+    assert abs(got[0, 0] - (2.0 + 3 * 2.0 ** -7 + 2.0 ** -14) / a) > 1e-5
+
+
+def test_planted_fused_scale_inside_rounding_fails(monkeypatch):
+    """Applying the row scale before the bf16 rounding (round(x nw s))
+    breaks the worked example (planted in a copy of the oracle)."""
+    def bad(x, nw, W, eps, sw=None):
+        x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+        nw = np.asarray(nw, dtype=np.float64).reshape(-1)
+        s = 1.0 / np.sqrt(np.mean(x * x, axis=1, keepdims=True) + eps)
+        xw = oracle.decode_bf16(oracle.round_bf16(x * nw * s))
+        return oracle.gemm(xw, W, b_nk=True, sb=sw)
+    monkeypatch.setattr(oracle, "rms_norm_matvec", bad)
+    with pytest.raises(AssertionError):
+        test_fused_norm_matvec_worked_rounding_example()
