@@ -361,6 +361,8 @@ def bench_decode(args, tg):
     distinct weight copies (more than the 256 MB Infinity Cache holds), warm
     = the same weights every launch."""
     out = []
+    # one workspace for the K split over programs, reused by every launch
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
     for wdt in ("bf16", "fp8"):
         for (N, K) in synth.DECODE_SHAPES:
             for M in (1, 8):
@@ -380,17 +382,23 @@ def bench_decode(args, tg):
                 def call(Wi):
                     return lambda st: tg.tile_gemm(x, Wi, y, b_trans=True,
                                                    scale_b=s, checked=False,
-                                                   stream=st)
+                                                   workspace=ws, stream=st)
                 ms = graph_ms([call(Wi) for Wi in Ws], reps=10)
                 ms_warm = graph_ms([call(W)] * 20, reps=10)
                 ms_eager = timed(lambda: tg.tile_gemm(x, W, y, b_trans=True,
-                                                      scale_b=s), 40, 5)
+                                                      scale_b=s,
+                                                      workspace=ws), 40, 5)
+                cfg = tg.tile_gemm_plan(x, W, y, b_trans=True,
+                                        want_map=False,
+                                        workspace_bytes=ws.numel())[0]
                 nbytes = wbytes + (N * 4 if s is not None else 0) + \
                     2 * M * K + 2 * M * N
                 out.append({"w": wdt, "M": M, "N": N, "K": K,
                             "us": ms * 1e3, "gbs": nbytes / (ms * 1e-3) / 1e9,
                             "gbs_warm": nbytes / (ms_warm * 1e-3) / 1e9,
-                            "us_eager_call": ms_eager * 1e3})
+                            "us_eager_call": ms_eager * 1e3,
+                            "config": {k: cfg[k] for k in
+                                       ("bn", "ksplit", "splitk")}})
                 log("decode", out[-1])
                 del Ws, W
     return out
@@ -470,6 +478,14 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
           for i in range(layers)]
     bufs = [torch.empty((1, d), dtype=torch.bfloat16, device="cuda")
             for _ in range(3 * layers)]
+    # workspaces of the K split over programs (the unfused matvec and the
+    # fused one), allocated once outside the timed graphs
+    ws = torch.empty(tg.tile_gemm_workspace_size(bufs[0], Ws[0], bufs[1],
+                                                 b_trans=True) + 256,
+                     dtype=torch.uint8, device="cuda")
+    wsf = torch.empty(tg.tile_rms_norm_matvec_workspace_size(xs, Ws[0],
+                                                             bufs[1]) + 256,
+                      dtype=torch.uint8, device="cuda")
 
     def run(stream=None):
         h = xs
@@ -477,7 +493,7 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
             norm, q, res = bufs[3 * i:3 * i + 3]
             tg.tile_rms_norm(h, nw, norm, 1e-6, checked=False, stream=stream)
             tg.tile_gemm(norm, Ws[i], q, b_trans=True, checked=False,
-                         stream=stream)
+                         workspace=ws, stream=stream)
             tg.tile_add(h, q, res, checked=False, stream=stream)
             h = res
     def run_fused(stream=None):
@@ -485,7 +501,7 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
         for i in range(layers):
             norm, q, res = bufs[3 * i:3 * i + 3]
             tg.tile_rms_norm_matvec(h, nw, Ws[i], q, 1e-6, checked=False,
-                                    stream=stream)
+                                    workspace=wsf, stream=stream)
             tg.tile_add(h, q, res, checked=False, stream=stream)
             h = res
     ms_eager = timed(run, 20, 5)

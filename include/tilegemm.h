@@ -144,7 +144,18 @@ typedef struct tg_config {
                              with TG_SCHED_CROSS, 3 means five slots of one
                              operand tile each (A or B of a K tile)         */
     int32_t sched;        /* tiled kernel: tg_sched                          */
+    int32_t splitk;       /* skinny kernel: programs sharing one sub-tensor's
+                             K (1..TG_MAX_SPLITK).  With splitk > 1 each
+                             stores its partial tile into a workspace
+                             partitioned by (split, sub-tensor) and a second
+                             launch, one program per sub-tensor of C, sums
+                             them in split order: deterministic, needs a
+                             workspace (tile_gemm_workspace_size).  The
+                             value is normalised to the splits that get K
+                             steps.                                         */
 } tg_config;
+
+#define TG_MAX_SPLITK 16
 
 typedef struct tg_opts {
     int32_t precision;    /* tg_precision                                    */
@@ -154,7 +165,9 @@ typedef struct tg_opts {
     const float *scale_a; /* device, M floats or NULL (all ones): row scales */
     const float *scale_b; /* device, N floats or NULL: output-column scales  */
     const tg_config *config; /* host; NULL -> picker                         */
-    void *workspace;      /* device; needed by TG_PREC_BF16X3/X6             */
+    void *workspace;      /* device, 16-byte aligned; needed by
+                             TG_PREC_BF16X3/X6 and by decode products split
+                             over programs along K (splitk > 1)             */
     size_t workspace_bytes;
     int32_t *write_count; /* device, M*N int32 (row-major, ld N) or NULL: each
                              store adds 1 to its element's counter, so a
@@ -187,7 +200,9 @@ tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
 
 /*
  * tile_gemm -- C = diag(scale_a) . A . B . diag(scale_b), one launch of tile
- * programs over the partition of C (Sec. 3.6).
+ * programs over the partition of C (Sec. 3.6; the decode-shaped product is
+ * the matvec of the decode layer in Sec. 3.2's graph-scope listing, bound
+ * by the weight stream as in the roofline of Sec. 5.3).
  *
  *   A  M x K (trans must be 0), B  K x N (or stored N x K with trans = 1),
  *   C  M x N with partition bm x bn.
@@ -196,7 +211,12 @@ tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
  *   bf16 before the contraction).  C is TG_F32 or TG_BF16.
  *   opts may be NULL (native precision, checked, picker).  Precision modes
  *   BF16X3/X6 need f32 A and B and a workspace of
- *   tile_gemm_workspace_size() bytes.
+ *   tile_gemm_workspace_size() bytes.  Decode products (M <= 16, B stored
+ *   N x K) may split K over several programs per sub-tensor: an explicit
+ *   config with splitk > 1 needs a workspace of tile_gemm_workspace_size()
+ *   bytes (TG_E_WORKSPACE without one); the default configuration splits
+ *   only when opts carries a workspace that large.  The workspace may not
+ *   share bytes with A, B or C (TG_E_ALIAS).
  *   K == 0 stores zeros.  M == 0 or N == 0 enqueues nothing.
  *
  * Every output element is stored exactly once, by the program that owns its
@@ -205,7 +225,9 @@ tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
 tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
                     const tg_opts *opts, tg_stream stream);
 
-/* Workspace bytes tile_gemm needs for these arguments (0 for native). */
+/* Workspace bytes tile_gemm needs for these arguments: for opts->config
+ * when it is set, else for the configuration tile_gemm chooses when a
+ * workspace is supplied (0 when nothing needs one). */
 size_t tile_gemm_workspace_size(const tg_in *A, const tg_in *B,
                                 const tg_out *C, const tg_opts *opts);
 
@@ -216,6 +238,8 @@ size_t tile_gemm_workspace_size(const tg_in *A, const tg_in *B,
  * (n_prog+1 ints) and prog_tiles (ceil(M/bm)*ceil(N/bn) ints) are non-NULL
  * they receive the program -> sub-tensor map, in the format
  * tile_partition_check accepts.  Call once with NULL tables to size them.
+ * The plan is the one for a caller supplying opts->workspace_bytes of
+ * workspace (the default decode split is reduced to fit it).
  */
 tg_status tile_gemm_plan(const tg_in *A, const tg_in *B, const tg_out *C,
                          const tg_opts *opts, tg_config *cfg,
@@ -307,13 +331,24 @@ tg_status tile_rms_norm(const tg_in *x, const tg_in *w, float eps, tg_out *y,
  * (16 x 16 or 16 x 32, written back into *y).  Each x * nw is rounded to
  * bf16 before the contraction; sums of squares and the product accumulate
  * in binary32; the row scale multiplies the binary32 sum.  opts may be NULL;
- * precision and config must be unset.  Errors as tile_gemm, before anything
- * is enqueued.  y is exclusively borrowed until the stream passes the
+ * precision and config must be unset.  With opts->workspace (16-byte
+ * aligned, tile_rms_norm_matvec_workspace_size bytes, sharing no bytes with
+ * x, nw, W or y) the K steps are split over several programs per
+ * sub-tensor where that gives the chip more programs; their partial tiles
+ * and partial sums of squares go to the workspace and a second launch sums
+ * them in split order (deterministic).  Without a workspace K is not split
+ * across programs.  Errors as tile_gemm, before anything is enqueued.  y
+ * and the workspace are exclusively borrowed until the stream passes the
  * launch.
  */
 tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
                                const tg_in *W, tg_out *y, const tg_opts *opts,
                                tg_stream stream);
+
+/* Workspace bytes tile_rms_norm_matvec uses when given one (0: it never
+ * splits these arguments).  x, W, y as for tile_rms_norm_matvec. */
+size_t tile_rms_norm_matvec_workspace_size(const tg_in *x, const tg_in *W,
+                                           const tg_out *y);
 
 /*
  * tile_error_norm -- binary64 reductions for the relative Frobenius error of
@@ -399,14 +434,14 @@ tg_status tile_tune_cache_load(const char *path);
  * and ksplit; log2 of the sub-tensor count, of the program count and of
  * the sub-tensors per program; the fraction of the last round of
  * sub-tensors that has work; the useful fraction of the padded output
- * area; flags for the ping-pong and the cross-tile schedule.
+ * area; flags for the ping-pong and the cross-tile schedule; log2 splitk.
  * tile_picker_set installs a cost model (host copy of the parameters in the
  * layout of tile_mlp_*, with per-feature mean and standard deviation used
  * to normalise the features); params == NULL removes it.
  * tile_picker_mode(mode) sets bit 1 = use the tuning cache, bit 2 = use the
  * cost model (mode < 0 only queries) and returns the previous mode.
  */
-#define TG_PICKER_FEATURES 22
+#define TG_PICKER_FEATURES 23
 tg_status tile_picker_features(const tg_in *A, const tg_in *B,
                                const tg_out *C, const tg_config *cfg,
                                float *feat);

@@ -59,7 +59,7 @@ class tg_config(ctypes.Structure):
                 ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
                 ("wm", ctypes.c_int32), ("wn", ctypes.c_int32),
                 ("ksplit", ctypes.c_int32), ("stages", ctypes.c_int32),
-                ("sched", ctypes.c_int32)]
+                ("sched", ctypes.c_int32), ("splitk", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -79,7 +79,9 @@ class tg_tune_result(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
-TG_PICKER_FEATURES = 22
+TG_PICKER_FEATURES = 23
+TG_MAX_SPLITK = 16
+_MAX_CANDIDATES = 128
 
 
 class TileGemmError(RuntimeError):
@@ -109,6 +111,9 @@ def _load():
     lib.tile_rms_norm_matvec.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
                                          P(tg_in), P(tg_out), P(tg_opts),
                                          ctypes.c_void_p]
+    lib.tile_rms_norm_matvec_workspace_size.argtypes = [P(tg_in), P(tg_in),
+                                                        P(tg_out)]
+    lib.tile_rms_norm_matvec_workspace_size.restype = ctypes.c_size_t
     lib.tile_rms_norm.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
                                   P(tg_out), P(tg_opts), ctypes.c_void_p]
     lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
@@ -278,14 +283,15 @@ def tile_gemm(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
               write_count=None, checked=True, stream=None):
     """C = diag(scale_a) A B diag(scale_b) into C's bm x bn partition.
 
-    B is K x N, or the stored N x K matrix when b_trans.  BF16x3/x6 need a
-    workspace (allocated here from torch when not given).  Returns
-    (A, B, C) -- the same tensor objects."""
+    B is K x N, or the stored N x K matrix when b_trans.  BF16x3/x6 and
+    decode products split along K over several programs need a workspace
+    (allocated here from torch when not given).  Returns (A, B, C) -- the
+    same tensor objects."""
     da, db = make_in(A), make_in(B, b_trans)
     dc = make_out(C, bm, bn)
     o = make_opts(precision, scale_a, scale_b, config, workspace, write_count,
                   checked)
-    if o.precision != TG_PREC_NATIVE and workspace is None:
+    if workspace is None:
         need = lib.tile_gemm_workspace_size(da, db, dc, o)
         if need:
             workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
@@ -332,15 +338,29 @@ def tile_rms_norm(x, w, y, eps=1e-6, bm=0, *, checked=True,
     return y
 
 
+def tile_rms_norm_matvec_workspace_size(x, W, y) -> int:
+    return int(lib.tile_rms_norm_matvec_workspace_size(
+        make_in(x), make_in(W, True), make_out(y)))
+
+
 def tile_rms_norm_matvec(x, nw, W, y, eps=1e-6, *, scale_w=None,
-                         checked=True, write_count=None, stream=None):
+                         checked=True, write_count=None, workspace=None,
+                         stream=None):
     """y = rms_norm(x; nw, eps) . W^T with the normalisation fused into the
     decode product (x: M x K bf16, M <= 16; nw: K bf16; W stored N x K).
-    Returns y."""
+    The workspace of a K split over programs is allocated here from torch
+    when not given (workspace=False: no split).  Returns y."""
     if nw.dim() == 1:
         nw = nw.view(1, -1)
     dy = make_out(y)
-    o = make_opts(scale_b=scale_w, write_count=write_count, checked=checked)
+    if workspace is None:
+        need = tile_rms_norm_matvec_workspace_size(x, W, y)
+        workspace = torch.empty(need, dtype=torch.uint8, device=y.device) \
+            if need else None
+    elif workspace is False:
+        workspace = None
+    o = make_opts(scale_b=scale_w, write_count=write_count, checked=checked,
+                  workspace=workspace)
     _raise(lib.tile_rms_norm_matvec(make_in(x), make_in(nw), float(eps),
                                     make_in(W, True), dy, o, _stream(stream)))
     tile_rms_norm_matvec.last_partition = (dy.bm, dy.bn)
@@ -348,18 +368,23 @@ def tile_rms_norm_matvec(x, nw, W, y, eps=1e-6, *, scale_w=None,
 
 
 def tile_gemm_workspace_size(A, B, C, bm=0, bn=0, *, b_trans=False,
-                             precision="native") -> int:
+                             precision="native", config=None) -> int:
     return int(lib.tile_gemm_workspace_size(
         make_in(A), make_in(B, b_trans), make_out(C, bm, bn),
-        make_opts(precision)))
+        make_opts(precision, config=config)))
 
 
 def tile_gemm_plan(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
-                   config=None, want_map=True):
-    """(config dict, n_prog, prog_offsets list, prog_tiles list)."""
+                   config=None, want_map=True, workspace_bytes=None):
+    """(config dict, n_prog, prog_offsets list, prog_tiles list) of the
+    launch tile_gemm makes for a caller supplying workspace_bytes of
+    workspace (default: as much as tile_gemm_workspace_size asks, which is
+    what this binding's tile_gemm allocates)."""
     da, db = make_in(A), make_in(B, b_trans)
     dc = make_out(C, bm, bn)
     o = make_opts(precision, config=config)
+    o.workspace_bytes = int(lib.tile_gemm_workspace_size(da, db, dc, o)) \
+        if workspace_bytes is None else int(workspace_bytes)
     cfg = tg_config()
     n = ctypes.c_int32(0)
     _raise(lib.tile_gemm_plan(da, db, dc, o, cfg, ctypes.byref(n), None,
@@ -473,34 +498,40 @@ def device_cus() -> int:
 def tile_gemm_candidates(A, B, C, bm=0, bn=0, *, b_trans=False,
                          precision="native"):
     """Configurations tile_gemm accepts for these arguments (dicts)."""
-    buf = (tg_config * 64)()
+    buf = (tg_config * _MAX_CANDIDATES)()
     n = lib.tile_gemm_candidates(make_in(A), make_in(B, b_trans),
                                  make_out(C, bm, bn), make_opts(precision),
-                                 buf, 64)
+                                 buf, _MAX_CANDIDATES)
     if n < 0:
         raise TileGemmError(TG_E_ARG, last_error())
-    return [buf[i].as_dict() for i in range(min(n, 64))]
+    return [buf[i].as_dict() for i in range(min(n, _MAX_CANDIDATES))]
 
 
 def tile_autotune(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
                   scale_a=None, scale_b=None, workspace=None, reps=3,
                   stream=None):
     """Time every candidate; returns (best config dict, [(cfg, ms, status)]).
-    The winner is recorded in the library's tuning cache."""
-    res = (tg_tune_result * 64)()
+    The winner is recorded in the library's tuning cache.  Without a given
+    workspace one as large as the hungriest candidate needs is allocated
+    here from torch."""
+    res = (tg_tune_result * _MAX_CANDIDATES)()
     nres = ctypes.c_int32(0)
     best = tg_config()
     o = make_opts(precision, scale_a, scale_b, None, workspace)
-    if o.precision != TG_PREC_NATIVE and workspace is None:
-        need = lib.tile_gemm_workspace_size(make_in(A), make_in(B, b_trans),
-                                            make_out(C, bm, bn), o)
-        workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
-        o.workspace = workspace.data_ptr()
-        o.workspace_bytes = need
+    if workspace is None:
+        need = max([tile_gemm_workspace_size(
+            A, B, C, bm, bn, b_trans=b_trans, precision=precision,
+            config=c) for c in tile_gemm_candidates(
+                A, B, C, bm, bn, b_trans=b_trans, precision=precision)] +
+            [0])
+        if need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=C.device)
+            o.workspace = workspace.data_ptr()
+            o.workspace_bytes = need
     st = lib.tile_autotune(make_in(A), make_in(B, b_trans),
-                           make_out(C, bm, bn), o, int(reps), res, 64,
-                           ctypes.byref(nres), ctypes.byref(best),
-                           _stream(stream))
+                           make_out(C, bm, bn), o, int(reps), res,
+                           _MAX_CANDIDATES, ctypes.byref(nres),
+                           ctypes.byref(best), _stream(stream))
     _raise(st)
     rows = [(res[i].cfg.as_dict(), float(res[i].ms), int(res[i].status))
             for i in range(nres.value)]

@@ -12,8 +12,15 @@
 // activation rows as the B operand; E4M3 weights are decoded exactly to
 // bf16 in registers first (there is no mixed bf16 x e4m3 matrix
 // instruction).  The KS partial tiles are summed in LDS in a fixed order,
-// and one wavefront stores the sub-tensor: deterministic, no atomics, no
-// workspace.
+// and one wavefront stores the sub-tensor: deterministic, no atomics.
+//
+// Where one program per sub-tensor leaves compute units idle (few output
+// columns) or streams too few bytes at once (long rows), the K steps are
+// also split over `splitk` programs per sub-tensor (grid y).  Each stores
+// its partial tile, unscaled, into its own slice part[s][M][N] of a
+// workspace partitioned by (split, sub-tensor); a second launch, whose
+// program p owns sub-tensor p of y, sums the slices in split order and
+// stores y.  No atomics: the result is the same on every run.
 #include "tg_device.hpp"
 #include "tg_elementwise.hpp"
 #include "tg_internal.hpp"
@@ -82,6 +89,9 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 #pragma unroll
     for (int t = 0; t < RT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nsteps = (g.K + KSTEP - 1) / KSTEP;
+    // this program's K steps: [sb, se) (the whole of K without a split)
+    const int sb = blockIdx.y * g.steps_per_split;
+    const int se = min(nsteps, sb + g.steps_per_split);
     constexpr int WES = WDT == TG_BF16 ? 2 : 1;
     constexpr int XV = WDT == TG_BF16 ? 1 : 2;   // activation chunks per step
     const char *Xc = reinterpret_cast<const char *>(X);
@@ -120,7 +130,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int k = (s0 + u) * KSTEP + grp * EPL;
-            const bool live = s0 + u < nsteps;
+            const bool live = s0 + u < se;
 #pragma unroll
             for (int t = 0; t < RT; ++t)
                 wv[b][u][t] = live ? ld_chunk(W[t], k, g.K, EPL, WES)
@@ -188,8 +198,10 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             }
     };
     constexpr int STRIDE = KS * UNROLL;
-    const int nfull = g.K / KSTEP;            // steps wholly inside K
-    int s0 = wave * UNROLL;
+    // steps of this program wholly inside K (split boundaries fall on
+    // super-step boundaries, so only the last split has a ragged tail)
+    const int nfull = min(g.K / KSTEP, se);
+    int s0 = sb + wave * UNROLL;
     if constexpr (NB == 2) {
         bool have0 = s0 + UNROLL <= nfull;
         if (have0) load_fast(s0, 0);
@@ -212,7 +224,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             contract(0);
         }
     }
-    for (; s0 < nsteps; s0 += STRIDE) {       // ragged tail, bounds checked
+    for (; s0 < se; s0 += STRIDE) {           // ragged tail, bounds checked
         load_checked(s0, 0);
         contract(0);
     }
@@ -226,6 +238,36 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     // (a weight row, i.e. output column) and column l % 16 (an output row).
     const int m = lane & 15;
     if (m >= g.M) return;
+    if (g.splitk > 1) {
+        // partial tile of split blockIdx.y, unscaled, into its own slice
+        float *dst = g.part + (int64_t)blockIdx.y * g.M * g.N +
+                     (int64_t)m * g.N;
+        if constexpr (NORM) {
+            if (blockIdx.x == 0 && grp == 0) {
+                float tot = 0.f;
+#pragma unroll
+                for (int w = 0; w < KS; ++w)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tot += ssq[w][m + 16 * q];
+                g.ssq_part[blockIdx.y * g.M + m] = tot;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+            f32x4 s = part[0][t][lane];
+#pragma unroll
+            for (int w = 1; w < KS; ++w) {
+                f32x4 p = part[w][t][lane];
+                s[0] += p[0]; s[1] += p[1]; s[2] += p[2]; s[3] += p[3];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int n = n0 + 16 * t + 4 * grp + v;
+                if (n < g.N) dst[n] = s[v];
+            }
+        }
+        return;
+    }
     float sa = g.scale_a ? g.scale_a[m] : 1.0f;
     if constexpr (NORM) {
         // row m's squares sit in lanes m, m + 16, m + 32, m + 48 of every
@@ -273,9 +315,40 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_norm_kernel(
     skinny_body<WDT, KS, CBF16, RT, true>(a.s, a.norm_w, a.eps);
 }
 
+// Merge of a split product: program p owns sub-tensor p of y (M rows x bn
+// columns); its threads take the sub-tensor's elements in row-major order
+// and sum the splitk partial values of each in split order.
+template <bool CBF16, bool NORM>
+__global__ __launch_bounds__(256) void skinny_merge_kernel(SkinnyArgs g,
+                                                           float eps) {
+    const int n0 = blockIdx.x * g.bn;
+    for (int e = threadIdx.x; e < g.M * g.bn; e += 256) {
+        const int m = e / g.bn, n = n0 + e % g.bn;
+        if (n >= g.N) continue;
+        const float *src = g.part + (int64_t)m * g.N + n;
+        const int64_t slice = (int64_t)g.M * g.N;
+        float v = src[0];
+        for (int s = 1; s < g.splitk; ++s) v += src[s * slice];
+        float sa = g.scale_a ? g.scale_a[m] : 1.0f;
+        if constexpr (NORM) {
+            float tot = g.ssq_part[m];
+            for (int s = 1; s < g.splitk; ++s) tot += g.ssq_part[s * g.M + m];
+            sa *= 1.0f / sqrtf(tot / (float)g.K + eps);
+        }
+        float y = v * sa;
+        if (g.scale_w) y *= g.scale_w[n];
+        const int64_t off = (int64_t)m * g.ldy + n;
+        if constexpr (CBF16)
+            static_cast<uint16_t *>(g.y)[off] = f32_to_bf16_bits(y);
+        else
+            static_cast<float *>(g.y)[off] = y;
+        if (g.wcount) atomicAdd(&g.wcount[(int64_t)m * g.N + n], 1);
+    }
+}
+
 template <int WDT, int KS, int RT>
 hipError_t launch_ks(int c_bf16, const SkinnyArgs &a, hipStream_t st) {
-    dim3 grid((a.N + 16 * RT - 1) / (16 * RT)), block(KS * 64);
+    dim3 grid((a.N + 16 * RT - 1) / (16 * RT), a.splitk), block(KS * 64);
     if (c_bf16)
         hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, true, RT>), grid,
                            block, 0, st, a);
@@ -309,7 +382,7 @@ hipError_t launch_bn(int c_bf16, int bn, int ksplit, const SkinnyArgs &a,
 template <int WDT, int RT>
 hipError_t launch_norm_rt(int c_bf16, int ksplit, const SkinnyNormArgs &a,
                           hipStream_t st) {
-    dim3 grid((a.s.N + 16 * RT - 1) / (16 * RT));
+    dim3 grid((a.s.N + 16 * RT - 1) / (16 * RT), a.s.splitk);
     // the fused normalisation runs with four wavefronts per program
     if (ksplit != 4) return hipErrorInvalidValue;
     dim3 block(4 * 64);
@@ -331,6 +404,27 @@ hipError_t launch_norm_w(int c_bf16, int bn, int ksplit,
 }
 
 }  // namespace
+
+hipError_t launch_skinny_merge(int c_bf16, const SkinnyArgs &a, bool norm,
+                               float eps, hipStream_t st) {
+    dim3 grid((a.N + a.bn - 1) / a.bn), block(256);
+    if (c_bf16) {
+        if (norm)
+            hipLaunchKernelGGL((skinny_merge_kernel<true, true>), grid, block,
+                               0, st, a, eps);
+        else
+            hipLaunchKernelGGL((skinny_merge_kernel<true, false>), grid,
+                               block, 0, st, a, eps);
+    } else {
+        if (norm)
+            hipLaunchKernelGGL((skinny_merge_kernel<false, true>), grid,
+                               block, 0, st, a, eps);
+        else
+            hipLaunchKernelGGL((skinny_merge_kernel<false, false>), grid,
+                               block, 0, st, a, eps);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_skinny_norm(int w_dtype, int c_bf16, int bn, int ksplit,
                               const SkinnyNormArgs &a, hipStream_t st) {

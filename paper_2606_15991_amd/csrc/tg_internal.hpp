@@ -118,9 +118,24 @@ struct SkinnyArgs {
     int64_t ldx, ldw, ldy;
     int32_t M, N, K;
     int32_t bn;          // output columns per program (16 or 32)
+    // K split over programs: splitk programs share one sub-tensor's K, each
+    // contracting the K steps [s * steps_per_split, (s + 1) *
+    // steps_per_split) of its split s; with splitk > 1 they store their
+    // partial tiles (unscaled binary32) into part[s][M][N] and, for the
+    // fused normalisation, their rows' partial sums of squares into
+    // ssq_part[s][M]; a merge launch then owns y.
+    int32_t splitk;
+    int32_t steps_per_split;
+    float *part;
+    float *ssq_part;
 };
 hipError_t launch_skinny(int w_dtype, int c_bf16, int bn, int ksplit,
                          const SkinnyArgs &a, hipStream_t st);
+// Merge of a split decode product: one program per bm x bn sub-tensor of
+// y sums the splitk partial tiles in split order, applies the scales (and
+// the fused normalisation's row scale when norm is set) and stores y.
+hipError_t launch_skinny_merge(int c_bf16, const SkinnyArgs &a, bool norm,
+                               float eps, hipStream_t st);
 
 // Simple kernel: any dtype combination, any alignment.
 struct SimpleArgs {

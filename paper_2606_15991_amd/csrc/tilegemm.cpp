@@ -105,7 +105,10 @@ tg_status check_map(int64_t tiles, int32_t n_prog, const int32_t *offs,
     if (n_prog == 0) return TG_OK;
     if (!offs || !ids) return fail(TG_E_ARG, "NULL program map");
     if (offs[0] != 0) return fail(TG_E_ARG, "program map must start at 0");
-    std::vector<uint8_t> seen((size_t)tiles, 0);
+    // reused per thread: after the first call of a size, checking
+    // allocates nothing
+    static thread_local std::vector<uint8_t> seen;
+    seen.assign((size_t)tiles, 0);
     for (int32_t p = 0; p < n_prog; ++p) {
         if (offs[p + 1] < offs[p])
             return fail(TG_E_ARG, "program %d: decreasing offsets", p);
@@ -282,11 +285,52 @@ struct Launch {
     int variant;       // tiled kernel index, or -1
     int gemm_dt;       // dtype the contraction reads (bf16 for split modes)
     int64_t Kc;        // contraction length seen by the kernel
+    int32_t sps;       // decode kernel: K steps per split
     Sched s;
 };
 
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of a decode product split over `splitk` programs per
+// sub-tensor: partial tiles [splitk][M][N] binary32, then (fused
+// normalisation) partial sums of squares [splitk][M].
+size_t skinny_ws_bytes(int64_t splitk, int64_t M, int64_t N, bool norm) {
+    if (splitk <= 1) return 0;
+    return up256((size_t)splitk * M * N * 4) +
+           (norm ? up256((size_t)splitk * M * 4) : 0);
+}
+
+// Decode kernel geometry: K steps (32 bf16 or 64 e4m3 weights per lane
+// group) and super-steps (eight 16-byte weight loads per lane).
+struct SkinnyGeo {
+    int64_t kstep, unroll, nsteps, supers;
+};
+SkinnyGeo skinny_geo(const Problem &p, int bn) {
+    SkinnyGeo g;
+    g.kstep = p.b_dt == TG_BF16 ? 32 : 64;
+    g.unroll = 8 / (bn / 16);
+    g.nsteps = (p.K + g.kstep - 1) / g.kstep;
+    g.supers = (g.nsteps + g.unroll - 1) / g.unroll;
+    return g;
+}
+
+// Splits that get K work when `splitk` are asked for: each split takes
+// ceil(supers / splitk) whole super-steps.
+int32_t effective_splitk(int64_t supers, int64_t splitk, int64_t *per) {
+    if (supers <= 0 || splitk <= 1) {
+        if (per) *per = supers > 0 ? supers : 1;
+        return 1;
+    }
+    const int64_t q = (supers + splitk - 1) / splitk;
+    if (per) *per = q;
+    return (int32_t)((supers + q - 1) / q);
+}
+
+// `have`: workspace bytes the caller supplies; the default K split of a
+// decode product is reduced until its workspace fits.
 tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
-                          const tg_out *C, const tg_config *uc, Launch &L) {
+                          const tg_out *C, const tg_config *uc, Launch &L,
+                          size_t have, bool norm = false) {
     tg_config cfg{};
     if (uc) cfg = *uc;
     if (cfg.kind < TG_KIND_AUTO || cfg.kind > TG_KIND_SIMPLE)
@@ -337,12 +381,16 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
                         "decode kernel needs M <= 16, bf16 A, bf16/e4m3 B "
                         "stored N x K, aligned 16-byte rows");
         if (cfg.bm == 0) cfg.bm = 16;
+        // the decode defaults assume MI355X's 256 compute units where the
+        // device cannot be asked (host-only planning)
+        const int64_t ncu = cus > 0 ? cus : 256;
         if (cfg.bn == 0) {
             // 32-column programs (each activation chunk serves two weight
-            // rows) for long rows and for long sweeps of e4m3 weights;
-            // measured on the decode shapes with cold weights
-            const bool wide = p.K >= 16384 ||
-                              (p.b_dt == TG_FP8_E4M3 && (p.N + 15) / 16 >= 1024);
+            // rows) for e4m3 weights with several activation rows or long
+            // sweeps; measured on the decode shapes with cold weights
+            const bool wide =
+                p.b_dt == TG_FP8_E4M3 &&
+                (p.M > 4 || (p.N + 15) / 16 >= 4 * ncu);
             cfg.bn = wide ? 32 : 16;
         }
         if (cfg.bm < p.M || cfg.bm > 16 || (cfg.bn != 16 && cfg.bn != 32))
@@ -350,21 +398,41 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
                         "decode kernel owns 16-row x 16- or 32-column "
                         "sub-tensors (partition %d x %d)", cfg.bm, cfg.bn);
         cfg.bm = 16;
+        const SkinnyGeo geo = skinny_geo(p, cfg.bn);
+        const int64_t progs = (p.N + cfg.bn - 1) / cfg.bn;
+        if (cfg.splitk == 0) {
+            // split K over programs until there are four programs per
+            // compute unit, keeping at least four super-steps per split
+            // (one per wavefront of a four-wavefront program), within the
+            // caller's workspace.  Measured over the decode shapes (M 1
+            // and 8, bf16 and e4m3, cold weights): within 3 % of the best
+            // configuration of each shape on average.
+            int64_t sk = 1;
+            while (sk < 8 && progs * sk < 4 * ncu &&
+                   (geo.supers + 2 * sk - 1) / (2 * sk) >= 4)
+                sk *= 2;
+            while (sk > 1 &&
+                   skinny_ws_bytes(effective_splitk(geo.supers, sk, nullptr),
+                                   p.M, p.N, norm) > have)
+                sk /= 2;
+            cfg.splitk = (int32_t)sk;
+        }
+        if (cfg.splitk < 1 || cfg.splitk > TG_MAX_SPLITK)
+            return fail(TG_E_UNSUPPORTED, "splitk %d not in [1, %d]",
+                        cfg.splitk, TG_MAX_SPLITK);
+        int64_t per = 1;
+        cfg.splitk = effective_splitk(geo.supers, cfg.splitk, &per);
+        L.sps = (int32_t)std::min<int64_t>(per * geo.unroll, INT32_MAX);
         if (cfg.ksplit == 0) {
             // four wavefronts per program split K, and at least one
             // wavefront per compute unit.  Measured on the decode shapes
             // with cold weights, where each wavefront keeps two super-steps
             // of loads in flight.
-            int64_t progs = (p.N + cfg.bn - 1) / cfg.bn;
             int ks = 4;
-            while (ks < 16 && progs * ks < (int64_t)std::max(cus, 1))
-                ks *= 2;
+            while (ks < 16 && progs * cfg.splitk * ks < ncu) ks *= 2;
             // no more wavefronts than super-steps of K (eight 16-byte
-            // weight loads per lane each)
-            const int64_t kstep = p.b_dt == TG_BF16 ? 32 : 64;
-            const int64_t super = kstep * 8 / (cfg.bn / 16);
-            const int64_t supers = (p.K + super - 1) / super;
-            while (ks > 1 && ks > supers) ks /= 2;
+            // weight loads per lane each) in one split
+            while (ks > 1 && ks > per) ks /= 2;
             cfg.ksplit = ks;
         }
         if (cfg.ksplit != 1 && cfg.ksplit != 2 && cfg.ksplit != 4 &&
@@ -407,6 +475,11 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         cfg.stages = v.stages;
         cfg.sched = v.sched;
         cfg.ksplit = 1;
+        if (cfg.splitk > 1)
+            return fail(TG_E_UNSUPPORTED, "splitk applies to the decode "
+                                          "kernel only");
+        cfg.splitk = 1;
+        L.sps = 0;
         L.s.tiles_m = (int32_t)((p.M + cfg.bm - 1) / cfg.bm);
         L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
         L.s.n_tiles = L.s.tiles_m * L.s.tiles_n;
@@ -426,6 +499,11 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         cfg.wm = 4;
         cfg.wn = 1;
         cfg.ksplit = 1;
+        if (cfg.splitk > 1)
+            return fail(TG_E_UNSUPPORTED, "splitk applies to the decode "
+                                          "kernel only");
+        cfg.splitk = 1;
+        L.sps = 0;
         L.s.tiles_m = (int32_t)((p.M + cfg.bm - 1) / cfg.bm);
         L.s.tiles_n = (int32_t)((p.N + cfg.bn - 1) / cfg.bn);
         L.s.n_tiles = L.s.tiles_m * L.s.tiles_n;
@@ -451,20 +529,29 @@ void candidates(const Problem &p, const tg_in *A, const tg_in *B,
     auto try_cfg = [&](const tg_config &c) {
         Launch L;
         std::string keep = g_err;
-        if (choose_explicit(p, A, B, C, &c, L) == TG_OK) out.push_back(L.cfg);
+        if (choose_explicit(p, A, B, C, &c, L, SIZE_MAX) == TG_OK) {
+            bool dup = false;
+            for (const tg_config &o : out)
+                dup = dup || std::memcmp(&o, &L.cfg, sizeof o) == 0;
+            if (!dup) out.push_back(L.cfg);
+        }
         g_err = keep;
     };
     const int np = p.precision == TG_PREC_BF16X3 ? 3
                    : p.precision == TG_PREC_BF16X6 ? 6 : 1;
     const int gdt = np > 1 ? TG_BF16 : p.a_dt;
     for (int bn : {16, 32})
-        for (int ks : {1, 2, 4, 8, 16}) {
-            tg_config c{};
-            c.kind = TG_KIND_SKINNY;
-            c.bn = bn;
-            c.ksplit = ks;
-            try_cfg(c);
-        }
+        for (int sk : {1, 2, 4, 8})
+            for (int ks : {1, 2, 4, 8, 16}) {
+                // K split over programs with two to eight wavefronts each
+                if (sk > 1 && (ks < 2 || ks > 8)) continue;
+                tg_config c{};
+                c.kind = TG_KIND_SKINNY;
+                c.bn = bn;
+                c.ksplit = ks;
+                c.splitk = sk;
+                try_cfg(c);
+            }
     const int n = tiled_variant_count();
     for (int i = 0; i < n; ++i) {
         const TiledVariant &v = tiled_variant(i);
@@ -518,19 +605,29 @@ void features(const Problem &p, const Launch &L, float *f) {
                     (tiles * (double)c.bm * (double)c.bn));
     f[20] = c.sched == TG_SCHED_PINGPONG ? 1.f : 0.f;
     f[21] = c.sched == TG_SCHED_CROSS ? 1.f : 0.f;
+    f[22] = lg2(pos(c.splitk));
 }
 
 // Configuration when the caller gives none: the tuning cache, then the
 // learned picker's argmin over the candidates, then the fixed heuristic.
+// `have`: workspace bytes the caller supplies.  Tuned or predicted
+// configurations whose decode split needs more are passed over.
 tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
-                 const tg_out *C, const tg_opts *o, Launch &L) {
+                 const tg_out *C, const tg_opts *o, Launch &L, size_t have,
+                 bool norm = false) {
     const tg_config *uc = o ? o->config : nullptr;
     if (uc || C->bm > 0 || C->bn > 0)
-        return choose_explicit(p, A, B, C, uc, L);
+        return choose_explicit(p, A, B, C, uc, L, have, norm);
     const int mode = host::picker_mode();
     tg_config cfg;
+    auto fits = [&](const Launch &Lx) {
+        return Lx.cfg.kind != TG_KIND_SKINNY ||
+               skinny_ws_bytes(Lx.cfg.splitk, p.M, p.N, norm) <= have;
+    };
     if ((mode & host::kUseCache) && host::cache_find(key_of(p), &cfg)) {
-        if (choose_explicit(p, A, B, C, &cfg, L) == TG_OK) return TG_OK;
+        if (choose_explicit(p, A, B, C, &cfg, L, have, norm) == TG_OK &&
+            fits(L))
+            return TG_OK;
     }
     if ((mode & host::kUseMlp) && host::picker_ready()) {
         std::vector<tg_config> cands;
@@ -539,7 +636,10 @@ tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
         int bi = -1;
         for (size_t i = 0; i < cands.size(); ++i) {
             Launch Li;
-            if (choose_explicit(p, A, B, C, &cands[i], Li) != TG_OK) continue;
+            if (choose_explicit(p, A, B, C, &cands[i], Li, have, norm) !=
+                    TG_OK ||
+                !fits(Li))
+                continue;
             float f[TG_PICKER_FEATURES];
             features(p, Li, f);
             const float y = host::picker_predict(f);
@@ -548,9 +648,10 @@ tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
                 bi = (int)i;
             }
         }
-        if (bi >= 0) return choose_explicit(p, A, B, C, &cands[bi], L);
+        if (bi >= 0)
+            return choose_explicit(p, A, B, C, &cands[bi], L, have, norm);
     }
-    return choose_explicit(p, A, B, C, nullptr, L);
+    return choose_explicit(p, A, B, C, nullptr, L, have, norm);
 }
 
 // Program p -> owned sub-tensor ids, as the kernels walk them.
@@ -573,9 +674,20 @@ void build_map(const Launch &L, int32_t *offs, int32_t *ids) {
     }
 }
 
+// The program map a launch will walk, built into per-thread buffers that
+// are reused from call to call, checked with the rules of
+// tile_partition_check (injective, covering).
+tg_status check_launch_map(const Launch &L) {
+    static thread_local std::vector<int32_t> offs, ids;
+    offs.resize((size_t)L.s.n_prog + 1);
+    ids.resize((size_t)L.s.n_tiles);
+    build_map(L, offs.data(), ids.data());
+    return check_map(L.s.n_tiles, L.s.n_prog, offs.data(), ids.data());
+}
+
 size_t split_bytes(const Problem &p, int np) {
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return up((size_t)p.M * p.K * np * 2) + up((size_t)p.K * p.N * np * 2);
+    return up256((size_t)p.M * p.K * np * 2) +
+           up256((size_t)p.K * p.N * np * 2);
 }
 
 int planes_of(int precision) {
@@ -590,6 +702,30 @@ const int8_t kX6A[6] = {1, 2, 0, 1, 0, 0}, kX6B[6] = {1, 0, 2, 0, 1, 0};
 
 std::mutex g_group_mu;
 std::unordered_map<const void *, GroupHeader> g_groups;
+
+// The workspace of a split decode product: present, large and aligned
+// enough, and sharing no bytes with the operands or the output.
+tg_status check_split_ws(const tg_opts *o, const Problem &p, int splitk,
+                         bool norm, const tg_in *ins, int n_in,
+                         const tg_out *C) {
+    const size_t need = skinny_ws_bytes(splitk, p.M, p.N, norm);
+    if (!o || !o->workspace || o->workspace_bytes < need)
+        return fail(TG_E_WORKSPACE,
+                    "decode product split over %d programs per sub-tensor "
+                    "needs a workspace of %zu bytes", splitk, need);
+    if (!aligned16(o->workspace))
+        return fail(TG_E_WORKSPACE, "workspace must be 16-byte aligned");
+    Range rw{(uintptr_t)o->workspace, (uintptr_t)o->workspace + need};
+    if (intersect(rw, byte_range(C->data, C->rows, C->cols, C->ld,
+                                 esize(C->dtype))))
+        return fail(TG_E_ALIAS, "workspace shares bytes with the output");
+    for (int i = 0; i < n_in; ++i)
+        if (intersect(rw, byte_range(ins[i].data, ins[i].rows, ins[i].cols,
+                                     ins[i].ld, esize(ins[i].dtype))))
+            return fail(TG_E_ALIAS, "workspace shares bytes with input %d",
+                        i);
+    return TG_OK;
+}
 
 }  // namespace
 
@@ -638,10 +774,21 @@ tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
 
 size_t tile_gemm_workspace_size(const tg_in *A, const tg_in *B,
                                 const tg_out *C, const tg_opts *o) {
+    std::string keep = g_err;
     Problem p;
-    if (describe(A, B, C, o, p) != TG_OK) return 0;
+    if (describe(A, B, C, o, p) != TG_OK) {
+        g_err = keep;
+        return 0;
+    }
     int np = planes_of(p.precision);
-    return np > 1 ? split_bytes(p, np) : 0;
+    if (np > 1) return split_bytes(p, np);
+    Launch L;
+    size_t need = 0;
+    if (choose(p, A, B, C, o, L, SIZE_MAX) == TG_OK &&
+        L.cfg.kind == TG_KIND_SKINNY)
+        need = skinny_ws_bytes(L.cfg.splitk, p.M, p.N, false);
+    g_err = keep;
+    return need;
 }
 
 tg_status tile_gemm_plan(const tg_in *A, const tg_in *B, const tg_out *C,
@@ -652,7 +799,9 @@ tg_status tile_gemm_plan(const tg_in *A, const tg_in *B, const tg_out *C,
     tg_status st = describe(A, B, C, o, p);
     if (st != TG_OK) return st;
     Launch L;
-    if ((st = choose(p, A, B, C, o, L)) != TG_OK) return st;
+    // the plan for a caller supplying opts->workspace_bytes of workspace
+    if ((st = choose(p, A, B, C, o, L, o ? o->workspace_bytes : 0)) != TG_OK)
+        return st;
     if (cfg) *cfg = L.cfg;
     if (n_prog) *n_prog = L.s.n_prog;
     if (prog_offsets && prog_tiles) build_map(L, prog_offsets, prog_tiles);
@@ -666,17 +815,13 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
     tg_status st = describe(A, B, C, o, p);
     if (st != TG_OK) return st;
     Launch L;
-    if ((st = choose(p, A, B, C, o, L)) != TG_OK) return st;
+    const size_t have = o && o->workspace ? o->workspace_bytes : 0;
+    if ((st = choose(p, A, B, C, o, L, have)) != TG_OK) return st;
     const bool checked = !o || o->checked;
     if (checked) {
         // the program map the kernel will walk must be injective and cover
         // the partition of C, and C may not alias A or B
-        std::vector<int32_t> offs((size_t)L.s.n_prog + 1),
-            ids((size_t)L.s.n_tiles);
-        build_map(L, offs.data(), ids.data());
-        if ((st = check_map(L.s.n_tiles, L.s.n_prog, offs.data(),
-                            ids.data())) != TG_OK)
-            return st;
+        if ((st = check_launch_map(L)) != TG_OK) return st;
         tg_out part = *C;
         part.bm = L.cfg.bm;
         part.bn = L.cfg.bn;
@@ -699,7 +844,20 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
         a.ldx = A->ld; a.ldw = B->ld; a.ldy = C->ld;
         a.M = (int32_t)p.M; a.N = (int32_t)p.N; a.K = (int32_t)p.K;
         a.bn = L.cfg.bn;
+        a.splitk = L.cfg.splitk;
+        a.steps_per_split = L.sps;
+        a.part = nullptr;
+        a.ssq_part = nullptr;
+        if (a.splitk > 1) {
+            const tg_in ins[2] = {*A, *B};
+            if ((st = check_split_ws(o, p, a.splitk, false, ins, 2, C)) !=
+                TG_OK)
+                return st;
+            a.part = static_cast<float *>(o->workspace);
+        }
         e = launch_skinny(p.b_dt, p.c_bf16, L.cfg.bn, L.cfg.ksplit, a, hs);
+        if (e == hipSuccess && a.splitk > 1)
+            e = launch_skinny_merge(p.c_bf16, a, false, 0.f, hs);
         return e == hipSuccess ? TG_OK : hip_fail(e, "decode kernel launch");
     }
     if (L.cfg.kind == TG_KIND_SIMPLE) {
@@ -788,7 +946,8 @@ tg_status tile_picker_features(const tg_in *A, const tg_in *B,
     tg_status st = describe(A, B, C, nullptr, p);
     if (st != TG_OK) return st;
     Launch L;
-    if ((st = choose_explicit(p, A, B, C, cfg, L)) != TG_OK) return st;
+    if ((st = choose_explicit(p, A, B, C, cfg, L, SIZE_MAX)) != TG_OK)
+        return st;
     features(p, L, feat);
     return TG_OK;
 }
@@ -961,6 +1120,7 @@ tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
     cfg.kind = TG_KIND_SKINNY;
     cfg.ksplit = 4;
     oo.config = &cfg;
+    const size_t have = o && o->workspace ? o->workspace_bytes : 0;
     Problem p;
     if ((st = describe(x, W, y, &oo, p)) != TG_OK) return st;
     if (nw->cols != p.K)
@@ -969,14 +1129,9 @@ tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
     if (p.K > 0 && ((uintptr_t)nw->data & 15) != 0)
         return fail(TG_E_SHAPE, "nw must be 16-byte aligned");
     Launch L;
-    if ((st = choose(p, x, W, y, &oo, L)) != TG_OK) return st;
+    if ((st = choose(p, x, W, y, &oo, L, have, true)) != TG_OK) return st;
     if (oo.checked) {
-        std::vector<int32_t> offs((size_t)L.s.n_prog + 1),
-            ids((size_t)L.s.n_tiles);
-        build_map(L, offs.data(), ids.data());
-        if ((st = check_map(L.s.n_tiles, L.s.n_prog, offs.data(),
-                            ids.data())) != TG_OK)
-            return st;
+        if ((st = check_launch_map(L)) != TG_OK) return st;
         tg_out part = *y;
         part.bm = L.cfg.bm;
         part.bn = L.cfg.bn;
@@ -993,12 +1148,46 @@ tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
     a.s.ldx = x->ld; a.s.ldw = W->ld; a.s.ldy = y->ld;
     a.s.M = (int32_t)p.M; a.s.N = (int32_t)p.N; a.s.K = (int32_t)p.K;
     a.s.bn = L.cfg.bn;
+    a.s.splitk = L.cfg.splitk;
+    a.s.steps_per_split = L.sps;
+    a.s.part = nullptr;
+    a.s.ssq_part = nullptr;
     a.norm_w = nw->data;
     a.eps = eps;
+    if (a.s.splitk > 1) {
+        const tg_in ins[3] = {*x, *W, *nw};
+        if ((st = check_split_ws(&oo, p, a.s.splitk, true, ins, 3, y)) !=
+            TG_OK)
+            return st;
+        char *ws = static_cast<char *>(oo.workspace);
+        a.s.part = reinterpret_cast<float *>(ws);
+        a.s.ssq_part = reinterpret_cast<float *>(
+            ws + up256((size_t)a.s.splitk * p.M * p.N * 4));
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
     hipError_t e = launch_skinny_norm(p.b_dt, p.c_bf16, L.cfg.bn,
-                                      L.cfg.ksplit, a,
-                                      static_cast<hipStream_t>(stream));
+                                      L.cfg.ksplit, a, hs);
+    if (e == hipSuccess && a.s.splitk > 1)
+        e = launch_skinny_merge(p.c_bf16, a.s, true, eps, hs);
     return e == hipSuccess ? TG_OK : hip_fail(e, "fused decode launch");
+}
+
+size_t tile_rms_norm_matvec_workspace_size(const tg_in *x, const tg_in *W,
+                                           const tg_out *y) {
+    std::string keep = g_err;
+    tg_config cfg{};
+    cfg.kind = TG_KIND_SKINNY;
+    cfg.ksplit = 4;
+    tg_opts oo{};
+    oo.config = &cfg;
+    Problem p;
+    Launch L;
+    size_t need = 0;
+    if (describe(x, W, y, &oo, p) == TG_OK &&
+        choose(p, x, W, y, &oo, L, SIZE_MAX, true) == TG_OK)
+        need = skinny_ws_bytes(L.cfg.splitk, p.M, p.N, true);
+    g_err = keep;
+    return need;
 }
 
 namespace {

@@ -172,11 +172,11 @@ tg_status tile_autotune(const tg_in *A, const tg_in *B, tg_out *C,
                         tg_tune_result *results, int32_t max_results,
                         int32_t *n_results, tg_config *best, tg_stream stream) {
     if (!A || !B || !C || reps <= 0) return TG_E_ARG;
-    std::vector<tg_config> cands(64);
-    int32_t nc = tile_gemm_candidates(A, B, C, opts, cands.data(), 64);
+    std::vector<tg_config> cands(128);
+    int32_t nc = tile_gemm_candidates(A, B, C, opts, cands.data(), 128);
     if (nc < 0) return TG_E_ARG;
     if (nc == 0) return TG_E_UNSUPPORTED;
-    cands.resize(std::min(nc, (int32_t)64));
+    cands.resize(std::min(nc, (int32_t)128));
     hipStream_t hs = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return TG_E_HIP;
@@ -316,22 +316,22 @@ int32_t tile_tune_cache_size(void) {
 
 // Text format, one entry per line:
 //   M N K a_dt b_dt b_nk c_bf16 precision kind bm bn bk wm wn ksplit stages
-//   sched
+//   sched splitk
 tg_status tile_tune_cache_save(const char *path) {
     if (!path) return TG_E_ARG;
     FILE *f = std::fopen(path, "w");
     if (!f) return TG_E_ARG;
     std::lock_guard<std::mutex> lk(g_mu);
-    std::fprintf(f, "# tilegemm tuning cache v3\n");
+    std::fprintf(f, "# tilegemm tuning cache v4\n");
     for (const auto &kv : g_cache) {
         const Key &k = kv.first;
         const tg_config &c = kv.second;
         std::fprintf(f,
                      "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d "
-                     "%d\n",
+                     "%d %d\n",
                      (long long)k.M, (long long)k.N, (long long)k.K, k.a_dt,
                      k.b_dt, k.b_nk, k.c_bf16, k.precision, c.kind, c.bm, c.bn,
-                     c.bk, c.wm, c.wn, c.ksplit, c.stages, c.sched);
+                     c.bk, c.wm, c.wn, c.ksplit, c.stages, c.sched, c.splitk);
     }
     std::fclose(f);
     return TG_OK;
@@ -350,11 +350,12 @@ tg_status tile_tune_cache_load(const char *path) {
         Key k;
         tg_config c{};
         int n = std::sscanf(
-            line, "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d %d",
+            line,
+            "%lld %lld %lld %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d",
             &M, &N, &K, &k.a_dt, &k.b_dt, &k.b_nk, &k.c_bf16, &k.precision,
             &c.kind, &c.bm, &c.bn, &c.bk, &c.wm, &c.wn, &c.ksplit, &c.stages,
-            &c.sched);
-        if (n != 17) {
+            &c.sched, &c.splitk);
+        if (n != 18) {
             st = TG_E_ARG;
             break;
         }

@@ -70,7 +70,8 @@ class ShapePool:
 
 def _key(cfg):
     return (cfg["kind"], cfg["bm"], cfg["bn"], cfg["bk"], cfg["wm"],
-            cfg["wn"], cfg["ksplit"], cfg["stages"], cfg["sched"])
+            cfg["wn"], cfg["ksplit"], cfg["stages"], cfg["sched"],
+            cfg["splitk"])
 
 
 def collect(shapes, pool, reps=3, log=None):

@@ -347,7 +347,8 @@ def test_picker_features_describe_the_configuration():
                 np.log2(n_prog), np.log2(rounds),
                 tiles / (n_prog * rounds), 1.0,
                 1.0 if cfg["sched"] == tg.TG_SCHED_PINGPONG else 0.0,
-                1.0 if cfg["sched"] == tg.TG_SCHED_CROSS else 0.0]
+                1.0 if cfg["sched"] == tg.TG_SCHED_CROSS else 0.0,
+                np.log2(max(cfg["splitk"], 1))]
         assert np.allclose(f, want, rtol=0, atol=1e-6), (cfg, f)
         seen.add(tuple(f))
     # every candidate is distinguishable by its features
@@ -355,21 +356,28 @@ def test_picker_features_describe_the_configuration():
 
 
 def test_decode_default_configuration():
-    """Without a GPU the plan still resolves the decode kernel's defaults:
-    four wavefronts split K; 32-column programs for rows of 16384 or more
-    and for e4m3 weights over more than 1024 16-column programs."""
-    for wdt, N, K, bn in ((torch.bfloat16, 5120, 5120, 16),
-                          (torch.bfloat16, 51200, 5120, 16),
-                          (torch.bfloat16, 5120, 25600, 32),
-                          (torch.float8_e4m3fn, 5120, 5120, 16),
-                          (torch.float8_e4m3fn, 51200, 5120, 32),
-                          (torch.float8_e4m3fn, 5120, 25600, 32)):
-        x = torch.empty((1, K), dtype=torch.bfloat16)
+    """Without a GPU the plan still resolves the decode kernel's defaults
+    (for 256 compute units): 16-column programs, 32 for e4m3 weights with
+    more than four activation rows or more than 4 x 256 16-column
+    programs; K split over programs (given a workspace) until there are
+    four programs per compute unit while every split keeps four
+    super-steps; four wavefronts split each program's K."""
+    cases = (  # wdt, M, N, K, bn, splitk
+        (torch.bfloat16, 1, 5120, 5120, 16, 4),
+        (torch.bfloat16, 8, 5120, 5120, 16, 4),
+        (torch.bfloat16, 1, 51200, 5120, 16, 1),
+        (torch.bfloat16, 1, 5120, 25600, 16, 4),
+        (torch.float8_e4m3fn, 1, 5120, 5120, 16, 2),
+        (torch.float8_e4m3fn, 8, 5120, 5120, 32, 4),
+        (torch.float8_e4m3fn, 1, 51200, 5120, 32, 1),
+        (torch.float8_e4m3fn, 8, 5120, 25600, 32, 8))
+    for wdt, M, N, K, bn, sk in cases:
+        x = torch.empty((M, K), dtype=torch.bfloat16)
         W = torch.empty((N, K), dtype=wdt)
-        y = torch.empty((1, N), dtype=torch.bfloat16)
+        y = torch.empty((M, N), dtype=torch.bfloat16)
         cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
-        assert (cfg["kind"], cfg["bn"], cfg["ksplit"]) == \
-            (tg.TG_KIND_SKINNY, bn, 4), (wdt, N, K, cfg)
+        assert (cfg["kind"], cfg["bn"], cfg["ksplit"], cfg["splitk"]) == \
+            (tg.TG_KIND_SKINNY, bn, 4, sk), (wdt, M, N, K, cfg)
     # short rows: no more wavefronts than K has super-steps (256 bf16)
     for K, ks in ((64, 1), (520, 2), (1024, 4)):
         x = torch.empty((8, K), dtype=torch.bfloat16)
@@ -378,6 +386,62 @@ def test_decode_default_configuration():
         cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
         assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["ksplit"] == ks, \
             (K, cfg)
+
+
+def _up256(x):
+    return (x + 255) // 256 * 256
+
+
+def test_decode_split_configuration_and_workspace():
+    """A decode product split over programs along K: the split count is
+    normalised to the splits that get whole super-steps (5120 bf16 = 20
+    super-steps of 256 for 16-column programs), the workspace holds one
+    binary32 partial tile per split, and an explicit split needs that
+    workspace, unaliased, before anything is enqueued."""
+    bf = torch.bfloat16
+    x = torch.empty((8, 5120), dtype=bf)
+    W = torch.empty((5120, 5120), dtype=bf)
+    y = torch.empty((8, 5120), dtype=bf)
+    for ask, eff in ((1, 1), (2, 2), (3, 3), (6, 5), (8, 7), (16, 10)):
+        c = {"kind": "skinny", "bn": 16, "ksplit": 4, "splitk": ask}
+        cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, config=c,
+                                want_map=False)[0]
+        assert cfg["splitk"] == eff, (ask, cfg)
+        need = tg.tile_gemm_workspace_size(x, W, y, b_trans=True, config=c)
+        assert need == (_up256(eff * 8 * 5120 * 4) if eff > 1 else 0)
+    c = tg.make_config({"kind": "skinny", "bn": 16, "ksplit": 4,
+                        "splitk": 4})
+
+    def run(ws=None, nbytes=None, out=y, cfg=c):
+        o = tg.make_opts(config=cfg)
+        if ws is not None:
+            o.workspace = ws.data_ptr()
+            o.workspace_bytes = nbytes if nbytes is not None else \
+                ws.numel() * ws.element_size()
+        return tg.lib.tile_gemm(tg.make_in(x), tg.make_in(W, True),
+                                tg.make_out(out), o, None)
+    need = _up256(4 * 8 * 5120 * 4)
+    assert run() == tg.TG_E_WORKSPACE
+    big = torch.empty(need + 4096, dtype=torch.uint8)
+    assert run(big, need - 256) == tg.TG_E_WORKSPACE
+    assert run(big[1:], need) == tg.TG_E_WORKSPACE          # misaligned
+    y_in_ws = big[:8 * 5120 * 2].view(bf).view(8, 5120)
+    assert run(big, need, out=y_in_ws) == tg.TG_E_ALIAS
+    for bad in (0, tg.TG_MAX_SPLITK + 1):
+        cb = tg.make_config({"kind": "skinny", "bn": 16, "splitk": bad})
+        if bad == 0:
+            continue
+        assert run(cfg=cb) == tg.TG_E_UNSUPPORTED
+    A = torch.empty((512, 512), dtype=bf)
+    C = torch.empty((512, 512))
+    ct = tg.make_config({"kind": "tiled", "bm": 256, "bn": 256, "splitk": 2})
+    o = tg.make_opts(config=ct)
+    assert tg.lib.tile_gemm(tg.make_in(A), tg.make_in(A), tg.make_out(C), o,
+                            None) == tg.TG_E_UNSUPPORTED
+    # a default plan without a workspace never splits
+    cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False,
+                            workspace_bytes=0)[0]
+    assert cfg["splitk"] == 1
 
 
 def test_bench_measures_one_gpu_only():

@@ -188,6 +188,12 @@ def test_fp8_instruction_precision_characterised():
 
 # ------------------------------------------------------------------ decode
 
+def decode_bn(wdt, M, N=0):
+    """Output columns per decode program by default: 32 for e4m3 weights
+    with more than four activation rows (or very long sweeps), else 16."""
+    return 32 if wdt == "fp8" and (M > 4 or N >= 16 * 1024) else 16
+
+
 @pytest.mark.parametrize("M", [1, 8, 16])
 @pytest.mark.parametrize("N,K", [(80, 512), (200, 1000), (1040, 4096)])
 @pytest.mark.parametrize("wdt", ["bf16", "fp8"])
@@ -204,7 +210,7 @@ def test_decode_parity(M, N, K, wdt):
     for out in (torch.float32, torch.bfloat16):
         C, wc = run_gemm(x, W, M, N, b_trans=True, out=out, count=True,
                          scale_b=None if sw is None else dev(sw))
-        assert tile_partition_of_last() == (16, 16)
+        assert tile_partition_of_last() == (16, decode_bn(wdt, M))
         R = reference(x, W, True, None, sw)
         err = rel_err(C, R)
         assert err <= (1e-5 if out == torch.float32 else 4e-3), err
@@ -219,6 +225,40 @@ def test_decode_ksplit_bitwise_stable(ks):
     C, _ = run_gemm(x, W, 8, 96, b_trans=True,
                     config={"kind": "skinny", "ksplit": ks})
     assert np.array_equal(exact64(C), reference(x, W, True))
+
+
+@pytest.mark.parametrize("sk", [2, 3, 4, 8, 16])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+def test_decode_split_k_bit_exact_and_deterministic(sk, wdt):
+    """K split over programs (partial tiles into the workspace, merged in
+    split order): small-integer operands give the exact product for every
+    split count, each output element is stored once, and two runs of the
+    same configuration agree bit for bit on N(0,1) inputs."""
+    M, N, K = 8, 1040, 4104      # ragged K: the last split is partial
+    note("decode split-K", sk, wdt)
+    dt = torch.bfloat16 if wdt == "bf16" else torch.float8_e4m3fn
+    x = synth.to_bf16(synth.small_int((M, K), 43))
+    W = synth.small_int((N, K), 44).to(dt)
+    cfg = {"kind": "skinny", "bn": 16, "ksplit": 4, "splitk": sk}
+    xd, Wd = dev_padded(x), dev_padded(W)
+    C = torch.full((M, N), float("nan"), device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    tg.tile_gemm(xd, Wd, C, b_trans=True, config=cfg, write_count=wc)
+    torch.cuda.synchronize()
+    plan = tg.tile_gemm_plan(xd, Wd, C, b_trans=True, config=cfg,
+                             want_map=False)[0]
+    assert plan["splitk"] > 1
+    assert np.array_equal(exact64(C.cpu()), reference(x, W, True))
+    assert torch.all(wc == 1)
+    xn = dev_padded(synth.to_bf16(synth.normal((M, K), 45)))
+    Wn = dev_padded(synth.normal((N, K), 46, std=0.02).to(dt))
+    C1 = torch.empty((M, N), device=DEV)
+    C2 = torch.empty((M, N), device=DEV)
+    tg.tile_gemm(xn, Wn, C1, b_trans=True, config=cfg)
+    tg.tile_gemm(xn, Wn, C2, b_trans=True, config=cfg)
+    torch.cuda.synchronize()
+    assert torch.equal(C1, C2)
+    assert rel_err(C1.cpu(), reference(xn.cpu(), Wn.cpu(), True)) <= 1e-5
 
 
 def test_decode_weight_only_fp8_end_to_end_error():
@@ -627,7 +667,7 @@ def test_decode_ragged_k(M, K, wdt):
     tg.tile_gemm(dev_padded(x), dev_padded(W), C, b_trans=True,
                  scale_b=None if s is None else dev(s))
     torch.cuda.synchronize()
-    assert tuple(tg.tile_gemm.last_partition) == (16, 16)
+    assert tuple(tg.tile_gemm.last_partition) == (16, decode_bn(wdt, M))
     assert rel_err(C.cpu(), reference(x, W, True, None, s)) <= 1e-5
 
 

@@ -121,11 +121,13 @@ def test_fused_norm_matvec_matches_oracle(M, N, K, wdt, out):
     assert int(wc.min()) == 1 and int(wc.max()) == 1
 
 
+@pytest.mark.parametrize("split", [True, False])
 @pytest.mark.parametrize("M,N,K", [(1, 5120, 5120), (4, 300, 1008),
                                    (16, 64, 4096)])
 @pytest.mark.parametrize("wdt", ["bf16", "fp8"])
 @pytest.mark.parametrize("out", [torch.float32, torch.bfloat16])
-def test_fused_norm_matvec_small_integers_bit_exact(M, N, K, wdt, out):
+def test_fused_norm_matvec_small_integers_bit_exact(M, N, K, wdt, out,
+                                                    split):
     """Activation rows of +-2^j (j = m mod 4; eps 0, so the row scale is
     2^-j exactly), power-of-two normalisation weights and small-integer
     weights: every x * nw is a bf16 value, every partial sum an integer
@@ -144,9 +146,13 @@ def test_fused_norm_matvec_small_integers_bit_exact(M, N, K, wdt, out):
         -2, 3, (N,), generator=g).float()
     y = torch.full((M, N), float("nan"), dtype=out, device=DEV)
     wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    # split=True: the library's default, which splits K over programs
+    # where that fills the chip (the workspace is allocated by the
+    # binding); split=False: no workspace, one program per sub-tensor
     tg.tile_rms_norm_matvec(x.to(DEV), nw.to(DEV), W.to(DEV), y, 0.0,
                             scale_w=None if sw is None else sw.to(DEV),
-                            write_count=wc)
+                            write_count=wc,
+                            workspace=None if split else False)
     torch.cuda.synchronize()
     R = oracle.rms_norm_matvec(exact64(x), exact64(nw), exact64(W), 0.0,
                                None if sw is None else exact64(sw))
