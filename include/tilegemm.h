@@ -232,6 +232,27 @@ size_t tile_gemm_workspace_size(const tg_in *A, const tg_in *B,
                                 const tg_out *C, const tg_opts *opts);
 
 /*
+ * tile_gemm_noalloc -- tile_gemm for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Arguments, results and errors as tile_gemm, except
+ * that opts->workspace must be NULL (TG_E_ARG otherwise): wherever tile_gemm
+ * takes a workspace (BF16X3/X6 planes, a decode product split over programs
+ * along K) this call uses a scratch array of TG_NOALLOC_SCRATCH_BYTES that
+ * the library holds in each device's memory from its first use until the
+ * process ends.  A request whose workspace exceeds it fails with
+ * TG_E_WORKSPACE before anything is enqueued (the default decode split is
+ * reduced to fit).  Nothing in the scratch needs clearing: every byte a
+ * launch reads was written earlier by the same call.  All calls on one
+ * device share its scratch, so calls that overlap on one device (different
+ * streams, or host threads) race: serialise them.  No allocation, no
+ * synchronisation; the first call on a device resolves the scratch's
+ * address (a host-side query).
+ */
+#define TG_NOALLOC_SCRATCH_BYTES (8u << 20)
+tg_status tile_gemm_noalloc(const tg_in *A, const tg_in *B, tg_out *C,
+                            const tg_opts *opts, tg_stream stream);
+
+/*
  * tile_gemm_plan -- the configuration and program map tile_gemm would use
  * for these arguments, without launching.  cfg (host) receives the chosen
  * configuration and *n_prog the number of tile programs.  When prog_offsets

@@ -117,6 +117,8 @@ def _load():
     lib.tile_rms_norm.argtypes = [P(tg_in), P(tg_in), ctypes.c_float,
                                   P(tg_out), P(tg_opts), ctypes.c_void_p]
     lib.tile_gemm_workspace_size.restype = ctypes.c_size_t
+    lib.tile_gemm_noalloc.argtypes = [P(tg_in), P(tg_in), P(tg_out),
+                                      P(tg_opts), ctypes.c_void_p]
     lib.tile_gemm_plan.argtypes = [P(tg_in), P(tg_in), P(tg_out), P(tg_opts),
                                    P(tg_config), P(i32), ctypes.c_void_p,
                                    ctypes.c_void_p]
@@ -176,7 +178,8 @@ def _load():
               "tile_picker_set", "tile_picker_predict", "tile_mlp_forward",
               "tile_mlp_loss_grad", "tile_mlp_adam"):
         getattr(lib, f).restype = i32
-    for f in ("tile_partition_check", "tile_gemm", "tile_gemm_plan",
+    for f in ("tile_partition_check", "tile_gemm", "tile_gemm_noalloc",
+              "tile_gemm_plan",
               "tile_gemm_grouped_prepare", "tile_gemm_grouped",
               "tile_add", "tile_mul", "tile_rms_norm", "tile_rms_norm_matvec",
               "tile_error_norm"):
@@ -299,6 +302,25 @@ def tile_gemm(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
             o.workspace_bytes = need
     _raise(lib.tile_gemm(da, db, dc, o, _stream(stream)))
     tile_gemm.last_partition = (dc.bm, dc.bn)
+    return A, B, C
+
+
+TG_NOALLOC_SCRATCH_BYTES = 8 << 20
+
+
+def tile_gemm_noalloc(A, B, C, bm=0, bn=0, *, b_trans=False,
+                      precision="native", scale_a=None, scale_b=None,
+                      config=None, write_count=None, checked=True,
+                      stream=None):
+    """tile_gemm without any device allocation: where tile_gemm takes a
+    workspace the library's own per-device scratch is used (calls that
+    overlap on one device race on it).  Returns (A, B, C)."""
+    da, db = make_in(A), make_in(B, b_trans)
+    dc = make_out(C, bm, bn)
+    o = make_opts(precision, scale_a, scale_b, config, None, write_count,
+                  checked)
+    _raise(lib.tile_gemm_noalloc(da, db, dc, o, _stream(stream)))
+    tile_gemm_noalloc.last_partition = (dc.bm, dc.bn)
     return A, B, C
 
 

@@ -703,6 +703,34 @@ const int8_t kX6A[6] = {1, 2, 0, 1, 0, 0}, kX6B[6] = {1, 0, 2, 0, 1, 0};
 std::mutex g_group_mu;
 std::unordered_map<const void *, GroupHeader> g_groups;
 
+// Device scratch of the allocation-free entry point: one array per device
+// (each device holds its own copy at its own address), resolved once per
+// device with that device current.  In host code the array's name is
+// only a stand-in; the resolved address is the one kernels receive.
+__device__ __align__(256) char scratch[TG_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, void *> g_scratch_addr;
+
+tg_status scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return TG_OK;
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "scratch address");
+    if (!ptr) return fail(TG_E_HIP, "scratch address is NULL");
+    g_scratch_addr[dev] = ptr;
+    *out = ptr;
+    return TG_OK;
+}
+
 // The workspace of a split decode product: present, large and aligned
 // enough, and sharing no bytes with the operands or the output.
 tg_status check_split_ws(const tg_opts *o, const Problem &p, int splitk,
@@ -924,6 +952,29 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
     }
     e = launch_tiled(L.variant, g, hs);
     return e == hipSuccess ? TG_OK : hip_fail(e, "tiled kernel launch");
+}
+
+tg_status tile_gemm_noalloc(const tg_in *A, const tg_in *B, tg_out *C,
+                            const tg_opts *o, tg_stream stream) {
+    g_err.clear();
+    if (o && o->workspace)
+        return fail(TG_E_ARG, "the allocation-free call takes no workspace");
+    void *ptr = nullptr;
+    tg_status st = scratch_address(&ptr);
+    if (st != TG_OK) return st;
+    tg_opts oo{};
+    if (o)
+        oo = *o;
+    else
+        oo.checked = 1;
+    oo.workspace = ptr;
+    oo.workspace_bytes = TG_NOALLOC_SCRATCH_BYTES;
+    st = tile_gemm(A, B, C, &oo, stream);
+    if (st == TG_E_WORKSPACE)
+        g_err = "the allocation-free call's scratch holds " +
+                std::to_string((size_t)TG_NOALLOC_SCRATCH_BYTES) +
+                " bytes: " + g_err;
+    return st;
 }
 
 int32_t tile_gemm_candidates(const tg_in *A, const tg_in *B, const tg_out *C,
