@@ -581,7 +581,24 @@ def bench_exec_modes(args, tg, n_elems=2048, chain=(1, 10, 100, 1000),
                          "us_per_op_p75": float(np.percentile(times, 75))}
         out.append(res)
         log("exec modes", res)
-    return out
+    return {"python_ctypes": out, "cpp_driver": exec_modes_cpp(reps)}
+
+
+def exec_modes_cpp(reps=20):
+    """The same chains launched from compiled code through the C ABI (the
+    library's own per-call cost without Python's): the tg_exec_modes driver
+    built beside the library, run as a child process."""
+    import subprocess
+    exe = os.path.join(ROOT, "paper_2606_15991_amd", "tg_exec_modes")
+    if not os.path.exists(exe):
+        return {"error": "tg_exec_modes is not built"}
+    r = subprocess.run([exe, str(reps)], capture_output=True, text=True,
+                       timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-500:]}
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    log("exec modes (C++ driver)", res)
+    return res
 
 
 def bench_bimodal(args, tg, n=2000, stream_counts=(1, 2, 4, 8, 16, 32),

@@ -270,25 +270,48 @@ tg_status tile_gemm_plan(const tg_in *A, const tg_in *B, const tg_out *C,
 /*
  * Grouped GEMM: n independent problems C_i = A_i . B_i in ONE persistent
  * launch whose programs walk the concatenated sub-tensor lists of all
- * problems (the mapped-partition schedule applied across problems).
+ * problems: the mapped-partition schedule of Sec. 3.6 applied across
+ * problems, the batched counterpart of the launch-overhead study of
+ * Sec. 5.2 and of the GEMM queue of App. B.
  *
  * tile_gemm_grouped_prepare validates every problem (each with the rules of
  * tile_gemm, plus: no two outputs may share bytes, and no output may share
- * bytes with any input of the launch), picks each problem's configuration and
- * writes a problem table into the caller's device workspace with an
- * asynchronous copy on `stream`.  Not capturable (it copies host memory).
- * Supported: bf16 A and B, f32 or bf16 C, native precision.
- * tile_gemm_grouped enqueues the single launch that reads that table; it
- * allocates nothing and does not synchronise, so it may be captured into a
- * HIP graph and replayed.  Pointers inside the table are those given to
- * prepare; replays recompute the same outputs.
+ * bytes with any input of the launch), picks ONE tile configuration for the
+ * launch (opts->config when given, else 256 x 256 sub-tensors for large
+ * batches and 128 x 128 for small ones; every problem's partition is
+ * written back into C[i].bm / C[i].bn), writes the problem table into the
+ * caller's device workspace (tile_gemm_grouped_workspace_size(n) bytes,
+ * 16-byte aligned) with a copy on `stream` that has completed when prepare
+ * returns, and fills the caller's host plan with the launch parameters.
+ * Not capturable.  Supported: bf16 A and B, one B layout and one C dtype
+ * (f32 or bf16) for all problems, native precision, no scales.
+ * opts->write_count (device, or NULL) holds sum_i M_i * N_i int32
+ * counters, problem i's block (row-major, leading dimension N_i) after
+ * those of problems 0 .. i-1; each store adds 1 to its element's counter.
+ *
+ * tile_gemm_grouped enqueues the single launch described by the plan (which
+ * names its workspace); it allocates nothing and does not synchronise, so
+ * it may be captured into a HIP graph and replayed.  Pointers inside the
+ * table are those given to prepare; replays recompute the same outputs.
+ * The plan is the caller's: the library keeps nothing between the calls.
+ * A plan that prepare did not fill (or that was altered) gives TG_E_ARG.
  */
+typedef struct tg_grouped_plan {
+    const void *workspace; /* device table the plan describes              */
+    int32_t n;             /* problems                                     */
+    int32_t total_tiles;   /* sub-tensors of all problems                  */
+    int32_t n_prog;        /* persistent programs of the launch            */
+    int32_t variant;       /* kernel instantiation (library-internal)      */
+    uint64_t tag;          /* consistency tag over the fields above        */
+} tg_grouped_plan;
+
 size_t tile_gemm_grouped_workspace_size(int32_t n);
 tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
                                     const tg_in *B, tg_out *C,
                                     const tg_opts *opts, void *workspace,
-                                    size_t workspace_bytes, tg_stream stream);
-tg_status tile_gemm_grouped(void *workspace, tg_stream stream);
+                                    size_t workspace_bytes,
+                                    tg_grouped_plan *plan, tg_stream stream);
+tg_status tile_gemm_grouped(const tg_grouped_plan *plan, tg_stream stream);
 
 /*
  * tile_add -- z = x + y element by element (Sec. 2, the add of the first
@@ -427,19 +450,20 @@ tg_status tile_autotune(const tg_in *A, const tg_in *B, tg_out *C,
  * tile_autotune_grouped -- the autotuner for one grouped launch: every tiled
  * configuration the launch can run (bf16, the problems' B layout and C
  * type) is prepared into `workspace`, launched once (warm-up) and then
- * `reps` times on `stream`, timed with HIP events; the workspace is left
- * prepared with the fastest, which *best receives (host, may be NULL), and
- * C[i].bm / C[i].bn hold its partition.  Arguments as for
- * tile_gemm_grouped_prepare, whose opts->config it ignores.  Outputs are
- * written (any candidate's results).  Synchronises the stream: not
- * capturable.
+ * `reps` times on `stream`, timed with HIP events; the workspace and *plan
+ * are left prepared with the fastest, which *best receives (host, may be
+ * NULL), and C[i].bm / C[i].bn hold its partition.  Arguments as for
+ * tile_gemm_grouped_prepare, whose opts->config it ignores (and whose
+ * opts->write_count it does not apply while timing).  Outputs are written
+ * (any candidate's results).  Synchronises the stream: not capturable.
  */
 tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
                                 tg_out *C, const tg_opts *opts,
                                 void *workspace, size_t workspace_bytes,
                                 int32_t reps, tg_tune_result *results,
                                 int32_t max_results, int32_t *n_results,
-                                tg_config *best, tg_stream stream);
+                                tg_config *best, tg_grouped_plan *plan,
+                                tg_stream stream);
 
 /* Tuning cache: clear, count, save to / merge from a text file (host). */
 tg_status tile_tune_cache_clear(void);

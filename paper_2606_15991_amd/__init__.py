@@ -74,6 +74,12 @@ class tg_opts(ctypes.Structure):
                 ("write_count", ctypes.c_void_p)]
 
 
+class tg_grouped_plan(ctypes.Structure):
+    _fields_ = [("workspace", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("total_tiles", ctypes.c_int32), ("n_prog", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("tag", ctypes.c_uint64)]
+
+
 class tg_tune_result(ctypes.Structure):
     _fields_ = [("cfg", tg_config), ("ms", ctypes.c_float),
                 ("status", ctypes.c_int32)]
@@ -127,8 +133,9 @@ def _load():
     lib.tile_gemm_grouped_prepare.argtypes = [i32, P(tg_in), P(tg_in),
                                               P(tg_out), P(tg_opts),
                                               ctypes.c_void_p, ctypes.c_size_t,
+                                              P(tg_grouped_plan),
                                               ctypes.c_void_p]
-    lib.tile_gemm_grouped.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.tile_gemm_grouped.argtypes = [P(tg_grouped_plan), ctypes.c_void_p]
     lib.tile_error_norm.argtypes = [ctypes.c_void_p, i32, ctypes.c_void_p,
                                     ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_void_p]
@@ -149,7 +156,8 @@ def _load():
     lib.tile_autotune_grouped.argtypes = [i32, P(tg_in), P(tg_in), P(tg_out),
                                           P(tg_opts), vp, ctypes.c_size_t,
                                           i32, P(tg_tune_result), i32, P(i32),
-                                          P(tg_config), vp]
+                                          P(tg_config), P(tg_grouped_plan),
+                                          vp]
     lib.tile_autotune_grouped.restype = i32
     lib.tile_tune_cache_clear.argtypes = []
     lib.tile_tune_cache_size.argtypes = []
@@ -440,61 +448,76 @@ def tile_gemm_grouped_workspace_size(n: int) -> int:
 
 
 class GroupedLaunch:
-    """A prepared grouped launch: the device workspace holding its problem
-    table plus the tensors it borrows (kept alive while the launch exists)."""
+    """A prepared grouped launch: the host plan, the device workspace holding
+    its problem table, and the tensors it borrows (kept alive while the
+    launch exists)."""
 
-    def __init__(self, As, Bs, Cs, workspace, partitions):
+    def __init__(self, As, Bs, Cs, workspace, plan, partitions,
+                 write_count=None):
         self.As, self.Bs, self.Cs = As, Bs, Cs
         self.workspace = workspace
+        self.plan = plan
         self.partitions = partitions
+        self.write_count = write_count
+
+
+def _grouped_descs(As, Bs, Cs, b_trans):
+    n = len(As)
+    ia = (tg_in * n)(*[make_in(a) for a in As])
+    ib = (tg_in * n)(*[make_in(b, b_trans) for b in Bs])
+    oc = (tg_out * n)(*[make_out(c) for c in Cs])
+    return n, ia, ib, oc
 
 
 def tile_gemm_grouped_prepare(As, Bs, Cs, *, b_trans=False, config=None,
-                              workspace=None, stream=None) -> GroupedLaunch:
-    n = len(As)
-    ia = (tg_in * n)(*[make_in(a) for a in As])
-    ib = (tg_in * n)(*[make_in(b, b_trans) for b in Bs])
-    oc = (tg_out * n)(*[make_out(c) for c in Cs])
+                              workspace=None, write_count=None,
+                              stream=None) -> GroupedLaunch:
+    """Validate the problems and write their table; write_count (device
+    int32, sum of M_i * N_i counters, problem after problem) counts
+    stores."""
+    n, ia, ib, oc = _grouped_descs(As, Bs, Cs, b_trans)
     need = tile_gemm_grouped_workspace_size(n)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=Cs[0].device)
-    o = make_opts(config=config)
+    o = make_opts(config=config, write_count=write_count)
+    plan = tg_grouped_plan()
     _raise(lib.tile_gemm_grouped_prepare(
         n, ia, ib, oc, o, workspace.data_ptr(),
-        workspace.numel() * workspace.element_size(), _stream(stream)))
-    return GroupedLaunch(As, Bs, Cs, workspace,
-                         [(oc[i].bm, oc[i].bn) for i in range(n)])
+        workspace.numel() * workspace.element_size(), ctypes.byref(plan),
+        _stream(stream)))
+    return GroupedLaunch(As, Bs, Cs, workspace, plan,
+                         [(oc[i].bm, oc[i].bn) for i in range(n)],
+                         write_count)
 
 
 def tile_autotune_grouped(As, Bs, Cs, *, b_trans=False, reps=3,
-                          workspace=None, stream=None):
+                          workspace=None, write_count=None, stream=None):
     """Time every tiled configuration of one grouped launch; returns
     (GroupedLaunch prepared with the fastest, best config dict,
     [(cfg, ms, status)])."""
-    n = len(As)
-    ia = (tg_in * n)(*[make_in(a) for a in As])
-    ib = (tg_in * n)(*[make_in(b, b_trans) for b in Bs])
-    oc = (tg_out * n)(*[make_out(c) for c in Cs])
+    n, ia, ib, oc = _grouped_descs(As, Bs, Cs, b_trans)
     need = tile_gemm_grouped_workspace_size(n)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=Cs[0].device)
-    res = (tg_tune_result * 64)()
+    res = (tg_tune_result * _MAX_CANDIDATES)()
     nres = ctypes.c_int32(0)
     best = tg_config()
+    plan = tg_grouped_plan()
     _raise(lib.tile_autotune_grouped(
-        n, ia, ib, oc, make_opts(), workspace.data_ptr(),
-        workspace.numel() * workspace.element_size(), int(reps), res, 64,
-        ctypes.byref(nres), ctypes.byref(best), _stream(stream)))
+        n, ia, ib, oc, make_opts(write_count=write_count),
+        workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+        int(reps), res, _MAX_CANDIDATES, ctypes.byref(nres),
+        ctypes.byref(best), ctypes.byref(plan), _stream(stream)))
     rows = [(res[i].cfg.as_dict(), float(res[i].ms), int(res[i].status))
             for i in range(nres.value)]
-    launch = GroupedLaunch(As, Bs, Cs, workspace,
-                           [(oc[i].bm, oc[i].bn) for i in range(n)])
+    launch = GroupedLaunch(As, Bs, Cs, workspace, plan,
+                           [(oc[i].bm, oc[i].bn) for i in range(n)],
+                           write_count)
     return launch, best.as_dict(), rows
 
 
 def tile_gemm_grouped(launch: GroupedLaunch, stream=None):
-    _raise(lib.tile_gemm_grouped(launch.workspace.data_ptr(),
-                                 _stream(stream)))
+    _raise(lib.tile_gemm_grouped(ctypes.byref(launch.plan), _stream(stream)))
     return launch.Cs
 
 

@@ -42,6 +42,12 @@ def _compile(src, verbose):
     return obj
 
 
+# Benchmark driver of the execution-mode measurement (a separate program
+# linked against the library, not part of it).
+EXEC_MODES_SRC = "exec_modes.cpp"
+EXEC_MODES_BIN = os.path.join(PKG, "tg_exec_modes")
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -52,6 +58,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+           os.path.join(CSRC, EXEC_MODES_SRC), "-o", EXEC_MODES_BIN + ".tmp",
+           "-L", PKG, "-ltilegemm", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(EXEC_MODES_BIN + ".tmp", EXEC_MODES_BIN)
     return LIB
 
 

@@ -1569,7 +1569,7 @@ struct GroupProvider {
         j.a = static_cast<const char *>(pb.a);
         j.b = static_cast<const char *>(pb.b);
         j.c = pb.c;
-        j.scale_a = nullptr; j.scale_b = nullptr; j.wcount = nullptr;
+        j.scale_a = nullptr; j.scale_b = nullptr; j.wcount = pb.wcount;
         j.lda = pb.lda; j.ldb = pb.ldb; j.ldc = pb.ldc;
         j.M = pb.M; j.N = pb.N; j.K = pb.K;
         j.m0 = tm * C::BM; j.n0 = tn * C::BN;
@@ -1742,14 +1742,14 @@ hipError_t launch_tiled(int variant, const GemmArgs &args, hipStream_t st) {
                            params, e.smem, st);
 }
 
-hipError_t launch_grouped(int variant, const GroupHeader *hdr,
-                          const void *table_dev, hipStream_t st) {
+hipError_t launch_grouped(int variant, int n_problems, int total_tiles,
+                          int n_prog, const void *table_dev, hipStream_t st) {
     int n;
     const VariantEntry &e = table(&n)[variant];
     hipError_t err = prepare_smem(e);
     if (err != hipSuccess) return err;
     const GroupProblem *tab = static_cast<const GroupProblem *>(table_dev);
-    int np = hdr->n, total = hdr->total_tiles, G = hdr->n_prog;
+    int np = n_problems, total = total_tiles, G = n_prog;
     void *params[] = {&tab, &np, &total, &G};
     return hipLaunchKernel(e.grouped, dim3(G), dim3(e.threads), params,
                            e.smem, st);

@@ -77,16 +77,7 @@ struct GroupProblem {
     int32_t tile_begin;  // prefix sum of tile counts, in table order
     int32_t c_bf16;      // output dtype: 0 f32, 1 bf16
     int32_t b_nk;        // B stored N x K
-};
-
-struct GroupHeader {
-    int32_t n;            // problems
-    int32_t total_tiles;
-    int32_t n_prog;
-    int32_t cfg_index;    // tiled-kernel variant shared by all problems
-    int32_t c_bf16;
-    int32_t b_nk;
-    int32_t reserved[2];
+    int32_t *wcount;     // M x N store counters (ld N) or NULL
 };
 
 // Tiled kernel variants (compile-time instantiations), by index.
@@ -103,7 +94,7 @@ int tiled_variant_count();
 const TiledVariant &tiled_variant(int i);
 // Enqueue variant i; returns hipSuccess or the launch error.
 hipError_t launch_tiled(int variant, const GemmArgs &args, hipStream_t st);
-hipError_t launch_grouped(int variant, const GroupHeader *hdr_host,
+hipError_t launch_grouped(int variant, int n, int total_tiles, int n_prog,
                           const void *table_dev, hipStream_t st);
 int tiled_occupancy(int variant);  // resident workgroups per CU
 

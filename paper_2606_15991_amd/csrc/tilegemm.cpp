@@ -700,8 +700,18 @@ int planes_of(int precision) {
 const int8_t kX3A[3] = {0, 1, 0}, kX3B[3] = {1, 0, 0};
 const int8_t kX6A[6] = {1, 2, 0, 1, 0, 0}, kX6B[6] = {1, 0, 2, 0, 1, 0};
 
-std::mutex g_group_mu;
-std::unordered_map<const void *, GroupHeader> g_groups;
+// Consistency tag of a grouped plan: a mix of its fields, so that a plan
+// prepare did not fill (or one altered since) is refused.
+uint64_t plan_tag(const tg_grouped_plan &pl) {
+    uint64_t h = 0x9e3779b97f4a7c15ull ^ (uint64_t)(uintptr_t)pl.workspace;
+    const int32_t f[4] = {pl.n, pl.total_tiles, pl.n_prog, pl.variant};
+    for (int32_t v : f) {
+        h ^= (uint64_t)(uint32_t)v + 0x9e3779b97f4a7c15ull + (h << 6) +
+             (h >> 2);
+        h *= 0xff51afd7ed558ccdull;
+    }
+    return h;
+}
 
 // Device scratch of the allocation-free entry point: one array per device
 // (each device holds its own copy at its own address), resolved once per
@@ -1013,18 +1023,20 @@ size_t tile_gemm_grouped_workspace_size(int32_t n) {
 tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
                                     const tg_in *B, tg_out *C,
                                     const tg_opts *o, void *ws,
-                                    size_t ws_bytes, tg_stream stream) {
+                                    size_t ws_bytes, tg_grouped_plan *plan,
+                                    tg_stream stream) {
     g_err.clear();
+    if (!plan) return fail(TG_E_ARG, "NULL plan");
     if (n <= 0 || !A || !B || !C) return fail(TG_E_ARG, "empty problem list");
     if (!ws) return fail(TG_E_WORKSPACE, "NULL workspace");
     if (ws_bytes < tile_gemm_grouped_workspace_size(n))
         return fail(TG_E_WORKSPACE, "workspace needs %zu bytes",
                     tile_gemm_grouped_workspace_size(n));
     if (!aligned16(ws)) return fail(TG_E_WORKSPACE, "workspace misaligned");
-    if (o && (o->precision != TG_PREC_NATIVE || o->scale_a || o->scale_b ||
-              o->write_count))
+    if (o && (o->precision != TG_PREC_NATIVE || o->scale_a || o->scale_b))
         return fail(TG_E_UNSUPPORTED,
                     "grouped launch: native precision, no scales");
+    int32_t *wc = o ? o->write_count : nullptr;
     std::vector<Problem> ps((size_t)n);
     int c_bf16 = -1, b_nk = -1;
     int64_t maxM = 0, maxN = 0;
@@ -1095,6 +1107,10 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
         return ps[x].K > ps[y].K;
     });
+    // problem i's write counters follow those of problems 0 .. i-1
+    std::vector<int64_t> wc_off((size_t)n + 1, 0);
+    for (int32_t i = 0; i < n; ++i)
+        wc_off[i + 1] = wc_off[i] + ps[i].M * ps[i].N;
     std::vector<GroupProblem> tab((size_t)n);
     int64_t total = 0;
     for (int32_t r = 0; r < n; ++r) {
@@ -1108,45 +1124,43 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
         g.tile_begin = (int32_t)total;
         g.c_bf16 = c_bf16;
         g.b_nk = b_nk;
+        g.wcount = wc ? wc + wc_off[i] : nullptr;
         total += (int64_t)g.tiles_m * g.tiles_n;
     }
     if (total > INT32_MAX) return fail(TG_E_SHAPE, "too many sub-tensors");
-    GroupHeader h{};
-    h.n = n;
-    h.total_tiles = (int32_t)total;
+    tg_grouped_plan pl{};
+    pl.workspace = ws;
+    pl.n = n;
+    pl.total_tiles = (int32_t)total;
     int cus = device_cus();
     int occ = cus > 0 ? tiled_occupancy(variant) : 1;
-    h.n_prog = (int32_t)std::min<int64_t>(total,
-                                          (int64_t)(cus > 0 ? cus : 256) * occ);
-    if (h.n_prog < 1) h.n_prog = 1;
-    h.cfg_index = variant;
-    h.c_bf16 = c_bf16;
-    h.b_nk = b_nk;
+    pl.n_prog = (int32_t)std::min<int64_t>(total,
+                                           (int64_t)(cus > 0 ? cus : 256) * occ);
+    if (pl.n_prog < 1) pl.n_prog = 1;
+    pl.variant = variant;
+    pl.tag = plan_tag(pl);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(ws, tab.data(), sizeof(GroupProblem) * n,
                                   hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "grouped table copy");
+    // the table lives in host memory owned by this call
     e = hipStreamSynchronize(hs);
     if (e != hipSuccess) return hip_fail(e, "grouped table copy");
-    std::lock_guard<std::mutex> lk(g_group_mu);
-    g_groups[ws] = h;
+    *plan = pl;
     return TG_OK;
 }
 
-tg_status tile_gemm_grouped(void *ws, tg_stream stream) {
+tg_status tile_gemm_grouped(const tg_grouped_plan *plan, tg_stream stream) {
     g_err.clear();
-    GroupHeader h;
-    {
-        std::lock_guard<std::mutex> lk(g_group_mu);
-        auto it = g_groups.find(ws);
-        if (it == g_groups.end())
-            return fail(TG_E_WORKSPACE,
-                        "workspace was not prepared by "
-                        "tile_gemm_grouped_prepare");
-        h = it->second;
-    }
-    if (h.total_tiles == 0) return TG_OK;
-    hipError_t e = launch_grouped(h.cfg_index, &h, ws,
+    if (!plan) return fail(TG_E_ARG, "NULL plan");
+    if (!plan->workspace || plan->tag != plan_tag(*plan) ||
+        plan->variant < 0 || plan->variant >= tiled_variant_count() ||
+        plan->n <= 0 || plan->total_tiles < 0 || plan->n_prog < 1)
+        return fail(TG_E_ARG,
+                    "plan was not filled by tile_gemm_grouped_prepare");
+    if (plan->total_tiles == 0) return TG_OK;
+    hipError_t e = launch_grouped(plan->variant, plan->n, plan->total_tiles,
+                                  plan->n_prog, plan->workspace,
                                   static_cast<hipStream_t>(stream));
     return e == hipSuccess ? TG_OK : hip_fail(e, "grouped kernel launch");
 }

@@ -234,8 +234,10 @@ tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
                                 void *workspace, size_t workspace_bytes,
                                 int32_t reps, tg_tune_result *results,
                                 int32_t max_results, int32_t *n_results,
-                                tg_config *best, tg_stream stream) {
-    if (n <= 0 || !A || !B || !C || !workspace || reps <= 0) return TG_E_ARG;
+                                tg_config *best, tg_grouped_plan *plan,
+                                tg_stream stream) {
+    if (n <= 0 || !A || !B || !C || !workspace || reps <= 0 || !plan)
+        return TG_E_ARG;
     const int b_nk = B[0].trans, c_bf16 = C[0].dtype == TG_BF16;
     std::vector<tg_config> cands;
     for (int i = 0; i < tiled_variant_count(); ++i) {
@@ -264,13 +266,14 @@ tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
     for (size_t i = 0; i < cands.size(); ++i) {
         o.config = &cands[i];
         tg_status st = tile_gemm_grouped_prepare(n, A, B, C, &o, workspace,
-                                                 workspace_bytes, stream);
-        if (st == TG_OK) st = tile_gemm_grouped(workspace, stream);
+                                                 workspace_bytes, plan,
+                                                 stream);
+        if (st == TG_OK) st = tile_gemm_grouped(plan, stream);
         float ms = -1.f;
         if (st == TG_OK) {
             (void)hipEventRecord(e0, hs);
             for (int32_t r = 0; r < reps && st == TG_OK; ++r)
-                st = tile_gemm_grouped(workspace, stream);
+                st = tile_gemm_grouped(plan, stream);
             (void)hipEventRecord(e1, hs);
             if (hipEventSynchronize(e1) != hipSuccess) {
                 ret = TG_E_HIP;
@@ -296,8 +299,9 @@ tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
     if (ret != TG_OK) return ret;
     if (bi < 0) return TG_E_UNSUPPORTED;
     o.config = &cands[bi];
+    if (opts) o.write_count = opts->write_count;
     tg_status st = tile_gemm_grouped_prepare(n, A, B, C, &o, workspace,
-                                             workspace_bytes, stream);
+                                             workspace_bytes, plan, stream);
     if (st != TG_OK) return st;
     if (best) *best = cands[bi];
     return TG_OK;

@@ -388,6 +388,19 @@ def test_decode_default_configuration():
             (K, cfg)
 
 
+def test_grouped_plan_must_come_from_prepare():
+    """tile_gemm_grouped launches only plans that prepare filled: an empty
+    plan, and one altered after prepare, are refused on the host."""
+    plan = tg.tg_grouped_plan()
+    assert tg.lib.tile_gemm_grouped(ctypes.byref(plan), None) == tg.TG_E_ARG
+    assert tg.lib.tile_gemm_grouped(None, None) == tg.TG_E_ARG
+    plan.workspace = 4096
+    plan.n, plan.total_tiles, plan.n_prog, plan.variant = 2, 8, 8, 0
+    plan.tag = 12345
+    assert tg.lib.tile_gemm_grouped(ctypes.byref(plan), None) == tg.TG_E_ARG
+    assert "prepare" in tg.last_error()
+
+
 def _up256(x):
     return (x + 255) // 256 * 256
 

@@ -361,9 +361,13 @@ def test_grouped_c4_batch_graph_replayed():
     Bd = [dev(b) for b in Bs]
     Cs = [torch.full((m, n), float("nan"), device=DEV) for m, n, k in shapes]
     note("grouped c4 batch: prepare + launch")
-    launch = tg.tile_gemm_grouped_prepare(Ad, Bd, Cs)
+    wc = torch.zeros(sum(m * n for m, n, k in shapes), dtype=torch.int32,
+                     device=DEV)
+    launch = tg.tile_gemm_grouped_prepare(Ad, Bd, Cs, write_count=wc)
     tg.tile_gemm_grouped(launch)
     torch.cuda.synchronize()
+    # every element of every problem stored exactly once
+    assert int(wc.min()) == 1 and int(wc.max()) == 1
     eager = [c.clone() for c in Cs]
     rng = np.random.default_rng(4)
     for i, (m, n, k) in enumerate(shapes):
@@ -388,6 +392,8 @@ def test_grouped_c4_batch_graph_replayed():
         torch.cuda.synchronize()
         for i, (c, e) in enumerate(zip(Cs, eager)):
             assert torch.equal(c, e), (rep, i)
+    # one more store per element and replay
+    assert int(wc.min()) == 4 and int(wc.max()) == 4
 
 
 @pytest.mark.parametrize("b_trans", [True, False])
