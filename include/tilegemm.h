@@ -129,10 +129,15 @@ typedef enum tg_sched {
     TG_SCHED_PINGPONG = 2, /* two wavefront groups alternate between loading
                               and contracting, one phase apart; needs K a
                               multiple of 16 bytes of the operand type      */
-    TG_SCHED_CROSS = 3     /* lock-step with the hand-over barrier of the
+    TG_SCHED_CROSS = 3,    /* lock-step with the hand-over barrier of the
                               next K tile placed before the last K step of
                               the current one (bf16); the default for B
                               stored N x K                                  */
+    TG_SCHED_STAGED = 4    /* four wavefronts of 128 x 128 outputs; each K
+                              tile read from HBM into registers two tiles
+                              ahead and stored into a two-stage LDS ring
+                              (bf16, B stored N x K, binary32 output, no
+                              scales, K a multiple of 64)                   */
 } tg_sched;
 
 typedef struct tg_config {

@@ -72,6 +72,7 @@ struct Cfg {
     static constexpr int SCHED = SCH_;          // wavefront schedule
     static constexpr bool PP = SCH_ == TG_SCHED_PINGPONG;
     static constexpr bool XT = SCH_ == TG_SCHED_CROSS;
+    static constexpr bool STG = SCH_ == TG_SCHED_STAGED;
     static constexpr int BK = RBY / ES;         // K elements per K tile
     static constexpr int CPRW = RBY / 16;       // 16-byte chunks per row
     static constexpr int RPK = 1024 / RBY;      // rows per 1 KiB block
@@ -96,7 +97,9 @@ struct Cfg {
     static constexpr int NSLOT = NS + 1;
     static constexpr int SMEM =
         (SCH_ == TG_SCHED_CROSS && NS == 3 ? 5 * (STAGE / 2) : NS * STAGE) +
-        (DIRECT && SCH_ != TG_SCHED_CROSS ? NSLOT * SCALE_SLOT : 0);
+        (DIRECT && SCH_ != TG_SCHED_CROSS && SCH_ != TG_SCHED_STAGED
+             ? NSLOT * SCALE_SLOT
+             : 0);
     static constexpr int LPW = STAGE / 1024 / NW;   // 1 KiB loads per wave
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
     static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
@@ -131,6 +134,9 @@ struct Cfg {
                   "ping-pong: two groups of four wavefronts, >= 3 stages");
     static_assert(!XT || (DIRECT && DT == TG_BF16 && (BK / 16) % 2 == 0),
                   "cross-tile schedule: bf16, even number of K steps");
+    static_assert(!STG || (DT == TG_BF16 && BNK && RBY == 128 && NS == 2),
+                  "staged schedule: bf16, B stored N x K, 64-deep K tiles, "
+                  "two LDS stages");
 };
 
 // Row-major [rows][RBY bytes] operand stage: chunk c of row r sits at chunk
@@ -1523,6 +1529,218 @@ __device__ __forceinline__ void run_pingpong(const P &prov, char *smem) {
     if (grp == 0) phase_barrier();
 }
 
+// ------------------------------------------------- register-staged ring
+//
+// Staged schedule (bf16, A and B both k-contiguous, 64-deep K tiles): the
+// HBM reads of a K tile go into registers, two register sets deep, and
+// reach LDS through ordinary 16-byte LDS stores into a ring of two stages.
+// With four wavefronts of 128 x 128 outputs (accumulators in the AGPR
+// half of the register file) the fragment reads per MFMA are a third
+// lower than with eight wavefronts of 128 x 64, and every K tile is read
+// from HBM two tile periods before the MFMAs need it: at the start of tile
+// kt the registers of tile kt + 1 are stored into the free stage and the
+// reads of tile kt + 3 are issued into them, while tile kt + 2 is still in
+// flight in the other set.  One barrier per tile, before its last K step
+// (as in the cross-tile schedule): by then every wavefront holds the
+// tile's last fragments, and tile kt + 1 has been stored.
+//
+// Register-set indices must be compile-time constants, so tiles are taken
+// in pairs.  Each owned sub-tensor starts its own pipeline (the reads of
+// its first three tiles are issued after the previous sub-tensor's last
+// MFMAs); K must be a whole number of K tiles.  Every tile issues its
+// LDS stores and its reads unconditionally (reads past K are out of the
+// buffer's range: zeros, no memory access), so that the compiler's
+// load-counter bookkeeping sees the same order of outstanding reads on
+// every path into the loop and waits only for the older register set.
+
+// This wavefront's share of one K tile in registers: LPW chunks of 16
+// bytes per lane, lane l of 1 KiB block rb holding the chunk that belongs
+// at byte 16 l of the block (the layout of the direct loads).
+template <class C>
+struct StagedSet {
+    i32x4 v[C::LPW];
+};
+
+// Where this wavefront's chunks of one K tile come from: a buffer
+// resource per operand (rooted at the tile's first K column, formed in
+// scalar registers without branches), one vector offset per operand (block
+// i of the wavefront holds rows row + i * NW * RPK; the swizzle does not
+// change over multiples of 16 rows, so every block of a lane reads the
+// same logical chunk) and the scalar distance between blocks.
+struct StagedSrc {
+    __amdgpu_buffer_rsrc_t ra, rb;
+    uint32_t va, vb;
+    int sa, sb;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(
+    const char *base, int64_t bytes) {
+    const uint64_t p = reinterpret_cast<uint64_t>(base);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+    const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)bytes);
+    const int32_t bhi = __builtin_amdgcn_readfirstlane((int32_t)(bytes >> 32));
+    // clamp to [0, 2^31 - 1]: negative -> 0, at least 2^31 -> 2^31 - 1
+    const uint32_t n = bhi < 0 ? 0u
+                       : (bhi > 0 || blo > 0x7fffffffu) ? 0x7fffffffu : blo;
+    return __builtin_amdgcn_make_buffer_rsrc(
+        reinterpret_cast<void *>(((uint64_t)hi << 32) | lo), (short)0,
+        (int)n, 0x00020000);
+}
+
+template <class C>
+__device__ __forceinline__ StagedSrc staged_src(const Job &j, int k0,
+                                                int wave, int lane) {
+    static_assert((C::NW * C::RPK) % 16 == 0, "swizzle period");
+    StagedSrc s;
+    const int row = wave * C::RPK + lane / C::CPRW;
+    const int kc = (lane % C::CPRW) ^ swz_f<C>(row);
+    // tiles past K (the unconditional reads ahead of the last tiles) read
+    // an empty buffer: zeros, no memory access
+    const int64_t skip = (int64_t)k0 * C::ES;
+    const bool live = k0 < j.K;
+    s.ra = uniform_rsrc(j.a_row + skip, live ? j.a_rem - skip : 0);
+    s.rb = uniform_rsrc(j.b_row + skip, live ? j.b_rem - skip : 0);
+    s.va = (uint32_t)((row * j.lda + kc * C::EPC) * C::ES);
+    s.vb = (uint32_t)((row * j.ldb + kc * C::EPC) * C::ES);
+    s.sa = __builtin_amdgcn_readfirstlane(
+        (int)(C::NW * C::RPK * j.lda * C::ES));
+    s.sb = __builtin_amdgcn_readfirstlane(
+        (int)(C::NW * C::RPK * j.ldb * C::ES));
+    return s;
+}
+
+// Chunks [LO, HI) of this wavefront's share of a K tile into the register
+// set (chunk c < NA is A block c, else B block c - NA).
+template <class C, int LO, int HI>
+__device__ __forceinline__ void staged_read(const StagedSrc &src,
+                                            StagedSet<C> &s) {
+    constexpr int NA = C::BM / C::RPK / C::NW;   // A blocks per wavefront
+#pragma unroll
+    for (int c = LO; c < HI; ++c) {
+        if (c < NA)
+            s.v[c] = __builtin_bit_cast(
+                i32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                           src.ra, src.va, c * src.sa, 0));
+        else
+            s.v[c] = __builtin_bit_cast(
+                i32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                           src.rb, src.vb, (c - NA) * src.sb, 0));
+    }
+}
+
+template <class C, int LO, int HI>
+__device__ __forceinline__ void staged_write(char *stage, int wave, int lane,
+                                             const StagedSet<C> &s) {
+    constexpr int NA = C::BM / C::RPK / C::NW;
+#pragma unroll
+    for (int c = LO; c < HI; ++c) {
+        char *base = c < NA ? stage : stage + C::BM * C::RBY;
+        const int i = c < NA ? c : c - NA;
+        *reinterpret_cast<i32x4 *>(base + (i * C::NW + wave) * 1024 +
+                                   lane * 16) = s.v[c];
+    }
+}
+
+// The MFMAs of one K step with, slotted between them one by one, the
+// NREAD fragment reads, NWRITE LDS stores and NLOAD HBM reads issued just
+// before in program order.
+template <class C, int NREAD, int NWRITE, int NLOAD>
+__device__ __forceinline__ void staged_mfma(const i32x4 (&af)[C::FM],
+                                            const i32x4 (&bf)[C::FN],
+                                            f32x16 (&acc)[C::FM][C::FN]) {
+#pragma unroll
+    for (int q = 0; q < C::FM * C::FN; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (q < NREAD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        if (q < NWRITE) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        if (q < NLOAD) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < C::FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < C::FN; ++jj)
+            acc[i][jj] = mfma_bf16(af[i], bf[jj], acc[i][jj]);
+}
+
+// One K tile of the staged ring.  Tile kt (stage kt & 1) is contracted;
+// set X holds tile kt + 1, which goes into the other stage over the first
+// three K steps, each chunk's registers taking the matching chunk of tile
+// kt + 3 right after; the other set holds tile kt + 2 (in flight).
+template <class C>
+__device__ __forceinline__ void staged_tile(
+    const Job &j, char *smem, int kt, int nk, int wave, int lane, int wm,
+    int wn, StagedSet<C> &X, i32x4 (&fa)[2][C::FM], i32x4 (&fb)[2][C::FN],
+    f32x16 (&acc)[C::FM][C::FN]) {
+    static_assert(C::BK / 16 == 4 && C::LPW == 16, "four K steps, 16 chunks");
+    constexpr int NR = C::FM + C::FN;
+    char *st = smem + (kt & 1) * C::STAGE;
+    char *nx = smem + ((kt + 1) & 1) * C::STAGE;
+    const StagedSrc src = staged_src<C>(j, (kt + 3) * C::BK, wave, lane);
+    read_frags<C>(st, wm, wn, lane, 1, fa[1], fb[1]);
+    staged_write<C, 0, 6>(nx, wave, lane, X);
+    staged_read<C, 0, 6>(src, X);
+    staged_mfma<C, NR, 6, 6>(fa[0], fb[0], acc);
+    read_frags<C>(st, wm, wn, lane, 2, fa[0], fb[0]);
+    staged_write<C, 6, 11>(nx, wave, lane, X);
+    staged_read<C, 6, 11>(src, X);
+    staged_mfma<C, NR, 5, 5>(fa[1], fb[1], acc);
+    read_frags<C>(st, wm, wn, lane, 3, fa[1], fb[1]);
+    staged_write<C, 11, 16>(nx, wave, lane, X);
+    staged_read<C, 11, 16>(src, X);
+    staged_mfma<C, NR, 5, 5>(fa[0], fb[0], acc);
+    // hand-over: tile kt + 1 is stored by every wavefront, nobody reads
+    // tile kt any more (its last fragments are in registers)
+    __builtin_amdgcn_sched_barrier(0);
+    ring_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    if (kt + 1 < nk) read_frags<C>(nx, wm, wn, lane, 0, fa[0], fb[0]);
+    staged_mfma<C, NR, 0, 0>(fa[1], fb[1], acc);
+}
+
+template <class C, class P>
+__device__ __forceinline__ void run_staged(const P &prov, char *smem) {
+    static_assert(C::BK / 16 % 2 == 0, "even number of K steps");
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    f32x16 acc[C::FM][C::FN];
+    i32x4 fa[2][C::FM], fb[2][C::FN];
+    StagedSet<C> S0, S1;
+    for (int t = program_slot(blockIdx.x, G); t < total; t += G) {
+        const Job j = prov.job(t);
+        const int nk = (j.K + C::BK - 1) / C::BK;
+        zero_acc<C>(acc);
+        if (nk > 0) {
+            // pipeline start: tiles 0 and 1 into the sets, tile 0 into
+            // stage 0, tile 2 into set 0
+            staged_read<C, 0, C::LPW>(staged_src<C>(j, 0, wave, lane), S0);
+            staged_read<C, 0, C::LPW>(staged_src<C>(j, C::BK, wave, lane),
+                                      S1);
+            // the previous sub-tensor's reads of stage 0 ended at its
+            // last hand-over barrier
+            staged_write<C, 0, C::LPW>(smem, wave, lane, S0);
+            staged_read<C, 0, C::LPW>(
+                staged_src<C>(j, 2 * C::BK, wave, lane), S0);
+            ring_barrier();
+            read_frags<C>(smem, wm, wn, lane, 0, fa[0], fb[0]);
+            int kt = 0;
+            for (; kt + 1 < nk; kt += 2) {
+                staged_tile<C>(j, smem, kt, nk, wave, lane, wm, wn, S1, fa,
+                               fb, acc);
+                staged_tile<C>(j, smem, kt + 1, nk, wave, lane, wm, wn, S0,
+                               fa, fb, acc);
+            }
+            if (kt < nk)
+                staged_tile<C>(j, smem, kt, nk, wave, lane, wm, wn, S1, fa,
+                               fb, acc);
+        }
+        epilogue<C>(j, wm, wn, lane, acc, nullptr);
+    }
+}
+
 // One problem: traversal index -> owned sub-tensor.
 template <class C>
 struct SingleProvider {
@@ -1536,7 +1754,14 @@ struct SingleProvider {
         j.a = static_cast<const char *>(g.a);
         j.b = static_cast<const char *>(g.b);
         j.c = g.c;
-        j.scale_a = g.scale_a; j.scale_b = g.scale_b; j.wcount = g.wcount;
+        // staged programs apply no scales (the host never gives them any),
+        // which keeps their epilogue within the register budget
+        if constexpr (C::STG) {
+            j.scale_a = nullptr; j.scale_b = nullptr;
+        } else {
+            j.scale_a = g.scale_a; j.scale_b = g.scale_b;
+        }
+        j.wcount = g.wcount;
         j.lda = g.lda; j.ldb = g.ldb; j.ldc = g.ldc;
         j.M = g.M; j.N = g.N; j.K = g.K;
         j.m0 = tm * C::BM; j.n0 = tn * C::BN;
@@ -1586,6 +1811,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_tiled_kernel(
     SingleProvider<C> p{g};
     if constexpr (C::PP)
         run_pingpong<C>(p, smem);
+    else if constexpr (C::STG)
+        run_staged<C>(p, smem);
     else if constexpr (C::XT && C::NS == 5)
         run_direct_x5<C>(p, smem);
     else if constexpr (C::HALVES)
@@ -1606,6 +1833,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_grouped_kernel(
     GroupProvider<C> p{tab, n, total, G};
     if constexpr (C::PP)
         run_pingpong<C>(p, smem);
+    else if constexpr (C::STG)
+        run_staged<C>(p, smem);
     else if constexpr (C::XT && C::NS == 5)
         run_direct_x5<C>(p, smem);
     else if constexpr (C::HALVES)
@@ -1665,6 +1894,9 @@ VariantEntry make_entry() {
     make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, TG_SCHED_CROSS>>(), \
         make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, TG_SCHED_CROSS>>()
 
+#define TG_VARIANTS_STG(DT, BM, BN)                                           \
+    make_entry<Cfg<DT, BM, BN, 2, 2, true, false, 128, 2, TG_SCHED_STAGED>>()
+
 #define TG_VARIANTS_PP_NK(DT, BM, BN, RBY, NS)                                \
     make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, TG_SCHED_PINGPONG>>(),          \
         make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, TG_SCHED_PINGPONG>>()
@@ -1683,6 +1915,7 @@ const VariantEntry *table(int *count) {
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 128, 3),
         TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 5),
+        TG_VARIANTS_STG(TG_BF16, 256, 256),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2, 128, 2),

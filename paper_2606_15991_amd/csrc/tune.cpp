@@ -268,6 +268,8 @@ tg_status tile_autotune_grouped(int32_t n, const tg_in *A, const tg_in *B,
         tg_status st = tile_gemm_grouped_prepare(n, A, B, C, &o, workspace,
                                                  workspace_bytes, plan,
                                                  stream);
+        // a configuration these problems cannot run is not a candidate
+        if (st == TG_E_UNSUPPORTED) continue;
         if (st == TG_OK) st = tile_gemm_grouped(plan, stream);
         float ms = -1.f;
         if (st == TG_OK) {
