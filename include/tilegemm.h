@@ -259,7 +259,10 @@ tg_status tile_gemm_noalloc(const tg_in *A, const tg_in *B, tg_out *C,
 
 /*
  * tile_gemm_plan -- the configuration and program map tile_gemm would use
- * for these arguments, without launching.  cfg (host) receives the chosen
+ * for these arguments, without launching: the host-side derivation of the
+ * launch grid from the output partition (Sec. 3.4) and the mapped
+ * partition's program -> sub-tensor map (Sec. 3.6), exported so that the
+ * ownership rules of App. A can be checked on the very map that runs.  cfg (host) receives the chosen
  * configuration and *n_prog the number of tile programs.  When prog_offsets
  * (n_prog+1 ints) and prog_tiles (ceil(M/bm)*ceil(N/bn) ints) are non-NULL
  * they receive the program -> sub-tensor map, in the format
@@ -401,7 +404,10 @@ size_t tile_rms_norm_matvec_workspace_size(const tg_in *x, const tg_in *W,
 
 /*
  * tile_error_norm -- binary64 reductions for the relative Frobenius error of
- * a result against a binary64 reference, on the GPU:
+ * a result against a binary64 reference, on the GPU (the correctness check
+ * that accompanies the GEMM measurement of Sec. 5.1; the paper states its
+ * results against a reference without fixing the norm, the relative
+ * Frobenius norm is the reading):
  *   out[0] = sum (C[i] - R[i])^2,  out[1] = sum R[i]^2   over i < n
  * C: device, n elements of c_dtype (TG_F32 or TG_BF16), read as a dense
  * array (pass matrices with ld == cols); R: device, n binary64 values.
