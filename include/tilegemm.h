@@ -490,14 +490,15 @@ tg_status tile_tune_cache_load(const char *path);
  * and ksplit; log2 of the sub-tensor count, of the program count and of
  * the sub-tensors per program; the fraction of the last round of
  * sub-tensors that has work; the useful fraction of the padded output
- * area; flags for the ping-pong and the cross-tile schedule; log2 splitk.
+ * area; flags for the ping-pong and the cross-tile schedule; log2 splitk;
+ * a flag for the configuration the fixed heuristic would pick.
  * tile_picker_set installs a cost model (host copy of the parameters in the
  * layout of tile_mlp_*, with per-feature mean and standard deviation used
  * to normalise the features); params == NULL removes it.
  * tile_picker_mode(mode) sets bit 1 = use the tuning cache, bit 2 = use the
  * cost model (mode < 0 only queries) and returns the previous mode.
  */
-#define TG_PICKER_FEATURES 23
+#define TG_PICKER_FEATURES 24
 tg_status tile_picker_features(const tg_in *A, const tg_in *B,
                                const tg_out *C, const tg_config *cfg,
                                float *feat);

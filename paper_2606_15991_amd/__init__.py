@@ -86,7 +86,7 @@ class tg_tune_result(ctypes.Structure):
                 ("status", ctypes.c_int32)]
 
 
-TG_PICKER_FEATURES = 23
+TG_PICKER_FEATURES = 24
 TG_MAX_SPLITK = 16
 _MAX_CANDIDATES = 128
 

@@ -1642,19 +1642,31 @@ __device__ __forceinline__ void staged_write(char *stage, int wave, int lane,
     }
 }
 
-// The MFMAs of one K step with, slotted between them one by one, the
-// NREAD fragment reads, NWRITE LDS stores and NLOAD HBM reads issued just
-// before in program order.
+// MFMA slots of a K step that carry one of n evenly spaced instructions.
+constexpr uint32_t spread_slots(int n, int slots, int shift) {
+    uint32_t m = 0;
+    for (int i = 0; i < n; ++i) m |= 1u << ((i * slots / n + shift) % slots);
+    return m;
+}
+
+// The MFMAs of one K step with, slotted between them, the NREAD fragment
+// reads (one after each of the first NREAD MFMAs) and the NWRITE LDS
+// stores and NLOAD HBM reads issued just before in program order, spread
+// evenly over the step so that the stores do not arrive at the LDS in a
+// burst.
 template <class C, int NREAD, int NWRITE, int NLOAD>
 __device__ __forceinline__ void staged_mfma(const i32x4 (&af)[C::FM],
                                             const i32x4 (&bf)[C::FN],
                                             f32x16 (&acc)[C::FM][C::FN]) {
+    constexpr int NM = C::FM * C::FN;
+    constexpr uint32_t WS = spread_slots(NWRITE, NM, 0);
+    constexpr uint32_t LS = spread_slots(NLOAD, NM, 1);
 #pragma unroll
-    for (int q = 0; q < C::FM * C::FN; ++q) {
+    for (int q = 0; q < NM; ++q) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         if (q < NREAD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        if (q < NWRITE) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-        if (q < NLOAD) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+        if ((WS >> q) & 1u) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+        if ((LS >> q) & 1u) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
     }
 #pragma unroll
     for (int i = 0; i < C::FM; ++i)
@@ -1677,14 +1689,18 @@ __device__ __forceinline__ void staged_tile(
     char *st = smem + (kt & 1) * C::STAGE;
     char *nx = smem + ((kt + 1) & 1) * C::STAGE;
     const StagedSrc src = staged_src<C>(j, (kt + 3) * C::BK, wave, lane);
+    // one scheduling region per K step, so that each step's interleave
+    // pattern takes that step's instructions
     read_frags<C>(st, wm, wn, lane, 1, fa[1], fb[1]);
     staged_write<C, 0, 6>(nx, wave, lane, X);
     staged_read<C, 0, 6>(src, X);
     staged_mfma<C, NR, 6, 6>(fa[0], fb[0], acc);
+    __builtin_amdgcn_sched_barrier(0);
     read_frags<C>(st, wm, wn, lane, 2, fa[0], fb[0]);
     staged_write<C, 6, 11>(nx, wave, lane, X);
     staged_read<C, 6, 11>(src, X);
     staged_mfma<C, NR, 5, 5>(fa[1], fb[1], acc);
+    __builtin_amdgcn_sched_barrier(0);
     read_frags<C>(st, wm, wn, lane, 3, fa[1], fb[1]);
     staged_write<C, 11, 16>(nx, wave, lane, X);
     staged_read<C, 11, 16>(src, X);

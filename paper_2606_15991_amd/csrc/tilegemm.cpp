@@ -584,7 +584,11 @@ void candidates(const Problem &p, const tg_in *A, const tg_in *B,
 float lg2(double x) { return (float)std::log2(x < 1.0 ? 1.0 : x); }
 
 // Picker features of one (request, configuration) pair.
-void features(const Problem &p, const Launch &L, float *f) {
+// dflt: the configuration the fixed heuristic gives the same request; the
+// last feature flags the candidate that equals it, so that the model learns
+// its corrections relative to the heuristic.
+void features(const Problem &p, const Launch &L, const tg_config &dflt,
+              float *f) {
     const tg_config &c = L.cfg;
     const double tiles = L.s.n_tiles > 0 ? L.s.n_tiles : 1;
     const double progs = L.s.n_prog > 0 ? L.s.n_prog : 1;
@@ -614,6 +618,20 @@ void features(const Problem &p, const Launch &L, float *f) {
     f[20] = c.sched == TG_SCHED_PINGPONG ? 1.f : 0.f;
     f[21] = c.sched == TG_SCHED_CROSS ? 1.f : 0.f;
     f[22] = lg2(pos(c.splitk));
+    f[23] = std::memcmp(&c, &dflt, sizeof c) == 0 ? 1.f : 0.f;
+}
+
+// The heuristic's configuration for a request (what tile_gemm runs with
+// neither cache nor model), given a workspace; zeros when none applies.
+tg_config default_config(const Problem &p, const tg_in *A, const tg_in *B,
+                         const tg_out *C) {
+    Launch L0;
+    std::string keep = g_err;
+    tg_config d{};
+    if (choose_explicit(p, A, B, C, nullptr, L0, SIZE_MAX) == TG_OK)
+        d = L0.cfg;
+    g_err = keep;
+    return d;
 }
 
 // Configuration when the caller gives none: the tuning cache, then the
@@ -642,6 +660,7 @@ tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
         candidates(p, A, B, C, cands);
         float best = 0.f;
         int bi = -1;
+        const tg_config dflt = default_config(p, A, B, C);
         for (size_t i = 0; i < cands.size(); ++i) {
             Launch Li;
             if (choose_explicit(p, A, B, C, &cands[i], Li, have, norm) !=
@@ -649,7 +668,7 @@ tg_status choose(const Problem &p, const tg_in *A, const tg_in *B,
                 !fits(Li))
                 continue;
             float f[TG_PICKER_FEATURES];
-            features(p, Li, f);
+            features(p, Li, dflt, f);
             const float y = host::picker_predict(f);
             if (bi < 0 || y < best) {
                 best = y;
@@ -1017,7 +1036,7 @@ tg_status tile_picker_features(const tg_in *A, const tg_in *B,
     Launch L;
     if ((st = choose_explicit(p, A, B, C, cfg, L, SIZE_MAX)) != TG_OK)
         return st;
-    features(p, L, feat);
+    features(p, L, default_config(p, A, B, C), feat);
     return TG_OK;
 }
 

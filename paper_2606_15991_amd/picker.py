@@ -184,7 +184,10 @@ def evaluate(recs, pool):
             out.append({"shape": r["shape"], "best_ms": r["best_ms"],
                         "mlp_ms": pick["ms"], "default_ms": d_ms,
                         "fixed_ms": fx["ms"] if fx else None,
-                        "mlp_cfg": pick["cfg"], "default_cfg": dcfg})
+                        "mlp_cfg": pick["cfg"], "default_cfg": dcfg,
+                        "cands": [{"cfg": c["cfg"], "ms": c["ms"],
+                                   "pred": pr}
+                                  for c, pr in zip(r["cands"], preds)]})
     finally:
         tile_picker_mode(old)
     return out

@@ -334,6 +334,9 @@ def test_picker_features_describe_the_configuration():
     B = torch.empty((8192, 8192), dtype=torch.bfloat16)
     C = torch.empty((8192, 8192), dtype=torch.float32)
     seen = set()
+    old = tg.tile_picker_mode(0)
+    dflt = tg.tile_gemm_plan(A, B, C, b_trans=True, want_map=False)[0]
+    tg.tile_picker_mode(old)
     for cfg in tg.tile_gemm_candidates(A, B, C, b_trans=True):
         f = tg.tile_picker_features(A, B, C, cfg, b_trans=True)
         _, n_prog, _, _ = tg.tile_gemm_plan(A, B, C, b_trans=True,
@@ -348,7 +351,8 @@ def test_picker_features_describe_the_configuration():
                 tiles / (n_prog * rounds), 1.0,
                 1.0 if cfg["sched"] == tg.TG_SCHED_PINGPONG else 0.0,
                 1.0 if cfg["sched"] == tg.TG_SCHED_CROSS else 0.0,
-                np.log2(max(cfg["splitk"], 1))]
+                np.log2(max(cfg["splitk"], 1)),
+                1.0 if cfg == dflt else 0.0]
         assert np.allclose(f, want, rtol=0, atol=1e-6), (cfg, f)
         seen.add(tuple(f))
     # every candidate is distinguishable by its features
