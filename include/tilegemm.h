@@ -133,11 +133,16 @@ typedef enum tg_sched {
                               next K tile placed before the last K step of
                               the current one (bf16); the default for B
                               stored N x K                                  */
-    TG_SCHED_STAGED = 4    /* four wavefronts of 128 x 128 outputs; each K
+    TG_SCHED_STAGED = 4,   /* four wavefronts of 128 x 128 outputs; each K
                               tile read from HBM into registers two tiles
                               ahead and stored into a two-stage LDS ring
                               (bf16, B stored N x K, binary32 output, no
                               scales, K a multiple of 64)                   */
+    TG_SCHED_BULK = 5      /* four wavefronts of 128 x 128 outputs; each K
+                              tile's fragments read from LDS into registers
+                              in one burst a tile period ahead, freeing its
+                              stage for loads NS - 1 tiles ahead (bf16, B
+                              stored N x K, K a multiple of 16 bytes)       */
 } tg_sched;
 
 typedef struct tg_config {

@@ -73,6 +73,7 @@ struct Cfg {
     static constexpr bool PP = SCH_ == TG_SCHED_PINGPONG;
     static constexpr bool XT = SCH_ == TG_SCHED_CROSS;
     static constexpr bool STG = SCH_ == TG_SCHED_STAGED;
+    static constexpr bool BLK = SCH_ == TG_SCHED_BULK;
     static constexpr int BK = RBY / ES;         // K elements per K tile
     static constexpr int CPRW = RBY / 16;       // 16-byte chunks per row
     static constexpr int RPK = 1024 / RBY;      // rows per 1 KiB block
@@ -97,7 +98,9 @@ struct Cfg {
     static constexpr int NSLOT = NS + 1;
     static constexpr int SMEM =
         (SCH_ == TG_SCHED_CROSS && NS == 3 ? 5 * (STAGE / 2) : NS * STAGE) +
-        (DIRECT && SCH_ != TG_SCHED_CROSS && SCH_ != TG_SCHED_STAGED
+        (SCH_ == TG_SCHED_CROSS && NS == 2 ? 256 : 0) +
+        (DIRECT && SCH_ != TG_SCHED_CROSS && SCH_ != TG_SCHED_STAGED &&
+                 SCH_ != TG_SCHED_BULK
              ? NSLOT * SCALE_SLOT
              : 0);
     static constexpr int LPW = STAGE / 1024 / NW;   // 1 KiB loads per wave
@@ -105,6 +108,7 @@ struct Cfg {
     static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
     static_assert(NS == 2 || NS == 4 ||
                       (NS == 5 && SCH_ == TG_SCHED_CROSS && RBY == 64) ||
+                      (NS == 5 && SCH_ == TG_SCHED_BULK) ||
                       (NS == 3 && SCH_ == TG_SCHED_CROSS && RBY == 128 &&
                        BM == BN),
                   "ring of 2 or 4 stages, 5 of 64-byte rows, or 5 operand "
@@ -121,7 +125,7 @@ struct Cfg {
     static_assert(BNK || DT != TG_FP8_E4M3, "e4m3 B must be stored N x K");
     static_assert(!B_KMAJOR || CPR >= 4, "k-major B rows of >= 64 bytes");
     static_assert(DT != TG_FP8_E4M3 || BK >= 64, "e4m3 K tile >= 64");
-    static_assert(LPW * (NS - 2) < 64, "vmcnt range");
+    static_assert(LPW * (NS - 1) < 64, "vmcnt range");
     // Wavefronts per SIMD when LDS limits the workgroups per CU (160 KiB):
     // the register budget and scheduling target of the compiler.  Without
     // it the scheduler aims at a higher occupancy than LDS allows and
@@ -134,6 +138,10 @@ struct Cfg {
                   "ping-pong: two groups of four wavefronts, >= 3 stages");
     static_assert(!XT || (DIRECT && DT == TG_BF16 && (BK / 16) % 2 == 0),
                   "cross-tile schedule: bf16, even number of K steps");
+    static_assert(!BLK || (DT == TG_BF16 && BNK && NS >= 4 &&
+                           BK / 16 * (FM + FN) * 4 <= 128),
+                  "bulk schedule: bf16, B stored N x K, a ring of at least "
+                  "four stages, one K tile of fragments in 64 registers");
     static_assert(!STG || (DT == TG_BF16 && BNK && RBY == 128 && NS == 2),
                   "staged schedule: bf16, B stored N x K, 64-deep K tiles, "
                   "two LDS stages");
@@ -969,6 +977,45 @@ __device__ __forceinline__ void mfma_step(const i32x4 (&af)[C::FM],
             acc[i][jj] = mfma_bf16(af[i], bf[jj], acc[i][jj]);
 }
 
+
+#ifndef TG_L2_PF
+#define TG_L2_PF 0
+#endif
+
+// L2 warm-up of K tile k0 of one owned sub-tensor (B stored N x K): each
+// lane touches one 64-byte half of one 128-byte row segment with a 4-byte
+// load into a scratch LDS word that nothing reads, so the direct loads
+// issued for that tile later hit the XCD's L2.  The traversal map puts an
+// 8 x 4 block of sub-tensors on each XCD, so a program touches only the A
+// rows whose index is tn mod 4 and the B rows whose index is tm mod 8:
+// together the block's programs touch each line once.  Two instructions
+// per wavefront.
+template <class C>
+__device__ __forceinline__ void warm_l2(const Job &j, int k0, char *dummy,
+                                        int wave, int lane) {
+    constexpr int LA = 2 * (C::BM / 4) / C::NW;    // lanes per wave, A
+    constexpr int LB = 2 * (C::BN / 8) / C::NW;    // lanes per wave, B
+    static_assert(LA <= 64 && LB <= 64, "warm-up lanes");
+    const int pa = (j.n0 / C::BN) & 3, pb = (j.m0 / C::BM) & 7;
+    const int64_t skip = (int64_t)k0 * C::ES;
+    {
+        const i32x4 srd = make_srd(j.a_row + skip, sat_bytes(j.a_rem - skip));
+        const int idx = wave * LA + lane;
+        const int row = pa + 4 * (idx >> 1);
+        const uint32_t off = lane < LA
+            ? (uint32_t)(row * j.lda * C::ES + (idx & 1) * 64) : kOutOfRange;
+        dma4(srd, dummy, off);
+    }
+    {
+        const i32x4 srd = make_srd(j.b_row + skip, sat_bytes(j.b_rem - skip));
+        const int idx = wave * LB + lane;
+        const int row = pb + 8 * (idx >> 1);
+        const uint32_t off = lane < LB
+            ? (uint32_t)(row * j.ldb * C::ES + (idx & 1) * 64) : kOutOfRange;
+        dma4(srd, dummy, off);
+    }
+}
+
 // Cross-tile schedule (bf16).  The barrier that hands over K tile kt + 1
 // sits before the last K step of tile kt instead of after it: every
 // wavefront has read all of tile kt's fragments by then, so the stage of
@@ -982,6 +1029,7 @@ template <class C, class P>
 __device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
     constexpr int KK = C::BK / 16;                 // K steps per tile (even)
     constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
+    constexpr int PF = (C::NS == 2 && !C::B_KMAJOR) ? TG_L2_PF : 0;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
@@ -1017,6 +1065,7 @@ __device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
             read_frags<C>(stage(g), wm, wn, lane, 0, fa[0], fb[0]);
         }
         int pend_b = -1;      // tile whose B loads are still to be issued
+        bool pf_out = false;  // warm-up loads issued after the last tile's
         for (int kt = 0; kt < nk; ++kt) {
             char *st = stage(g + kt);
 #pragma unroll
@@ -1027,6 +1076,13 @@ __device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
                 if (kk == 0 && pend_b >= 0) {
                     issue_direct<C>(j, stage(g + pend_b), pend_b * C::BK,
                                     wave, lane, 2);
+                    if constexpr (PF > 0) {
+                        if (pend_b + PF < nk) {
+                            warm_l2<C>(j, (pend_b + PF) * C::BK,
+                                       smem + C::NS * C::STAGE, wave, lane);
+                            pf_out = true;
+                        }
+                    }
                     pend_b = -1;
                 }
             }
@@ -1039,7 +1095,11 @@ __device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
             // (pinned: the scheduler would otherwise hoist the barrier
             // above the MFMAs of the previous steps)
             __builtin_amdgcn_sched_barrier(0);
-            wait_tile<C>(later);
+            if (PF > 0 && pf_out)
+                wait_vmem_le<2>();   // all but the two warm-up loads
+            else
+                wait_tile<C>(later);
+            pf_out = false;
             ring_barrier();
             __builtin_amdgcn_sched_barrier(0);
             if (ragged && kt + 1 == nk - 1) {
@@ -1529,6 +1589,312 @@ __device__ __forceinline__ void run_pingpong(const P &prov, char *smem) {
     if (grp == 0) phase_barrier();
 }
 
+
+// ------------------------------------------------------- bulk-read ring
+//
+// Bulk-read schedule (bf16, A and B both k-contiguous).  A K tile's
+// fragments are read from LDS into registers all at once, one tile period
+// before they are contracted, so its LDS stage is free again as soon as
+// every wavefront has read it: with a ring of NS stages the direct loads
+// of a tile are issued NS - 1 tile periods before the tile is read (the
+// lead time that the HBM and L2 latency under full load asks for), and
+// each wavefront holds two tiles of fragments (the one being contracted
+// and the next).  Four wavefronts of 128 x 128 outputs, one per SIMD,
+// accumulators in the AGPR half of the register file.
+//
+// The loads run as one stream over the K tiles of all owned sub-tensors
+// (tile q of the stream in stage q % NS).  Iteration q, with tile q's
+// fragments in registers:
+//   wait: this wavefront's reads of tile q are complete and its loads of
+//         tile q + 1 have landed; barrier (so for every wavefront);
+//   issue the loads of tile q + NS into stage q % NS (tile q's, now free);
+//   read tile q + 1's fragments into the other register set, one read
+//   slotted after each of the first MFMAs of tile q;
+//   after the sub-tensor's last tile, store it and start the next.
+// Loads complete in issue order, so waiting until at most the loads of the
+// tiles issued after tile q + 1 are outstanding means tile q + 1 has
+// landed; epilogue stores in between only make that wait longer.
+
+// One 16-byte-per-lane load into LDS at `lds` + 16 * lane from buffer
+// `srd` at byte offset voff + soff (same protocol as dma16; the scalar
+// offset carries the distance between a wavefront's 1 KiB blocks).
+template <bool FIRST>
+__device__ __forceinline__ void dma16_so(const i32x4 &srd, uint32_t lds_,
+                                         uint32_t voff, int soff) {
+    const uint32_t lds = __builtin_amdgcn_readfirstlane(lds_);
+    if constexpr (FIRST)
+        asm volatile(
+            "s_nop 4\n\ts_mov_b32 m0, %0\n\ts_nop 0\n\t"
+            "buffer_load_dwordx4 %1, %2, %3 offen lds"
+            :
+            : "s"(lds), "v"(voff), "s"(srd), "s"(soff)
+            : "memory", "m0");
+    else
+        asm volatile(
+            "s_mov_b32 m0, %0\n\ts_nop 0\n\t"
+            "buffer_load_dwordx4 %1, %2, %3 offen lds"
+            :
+            : "s"(lds), "v"(voff), "s"(srd), "s"(soff)
+            : "memory", "m0");
+}
+
+// Load stream of one operand of one owned sub-tensor (rows k-contiguous):
+// first byte of its rows and the bytes from there to the operand's end,
+// the lane's offset within the wavefront's first 1 KiB block (block i of
+// the wavefront holds rows i * NW * RPK further down; the swizzle repeats
+// every 32 rows, so every block of a lane reads the same logical chunk)
+// and the distance between blocks.  K is a whole number of K tiles, so no
+// chunk straddles or passes K; rows beyond M / N lie past the buffer's
+// end and load zeros.
+struct BulkStream {
+    const char *row;
+    int64_t rem;
+    uint32_t voff;
+    int32_t stride;
+};
+
+template <class C>
+__device__ __forceinline__ BulkStream bulk_stream(const char *row0,
+                                                  int64_t rem, int64_t ld,
+                                                  int wave, int lane) {
+    static_assert((C::NW * C::RPK) % 32 == 0, "swizzle period");
+    BulkStream s;
+    const int row = wave * C::RPK + lane / C::CPRW;
+    const int kc = (lane % C::CPRW) ^ swz_f<C>(row);
+    s.row = row0;
+    s.rem = rem;
+    s.voff = (uint32_t)((row * ld + kc * C::EPC) * C::ES);
+    s.stride = __builtin_amdgcn_readfirstlane(
+        (int)(C::NW * C::RPK * ld * C::ES));
+    return s;
+}
+
+// This wavefront's ROWS / RPK / NW blocks of one operand of K tile k0.
+template <class C, int ROWS>
+__device__ __forceinline__ void bulk_issue(const BulkStream &s, int k0,
+                                           uint32_t dst, int wave) {
+    const int64_t skip = (int64_t)k0 * C::ES;
+    const i32x4 srd = make_srd(s.row + skip, sat_bytes(s.rem - skip));
+#pragma unroll
+    for (int i = 0; i < ROWS / C::RPK / C::NW; ++i) {
+        const uint32_t lds = dst + (uint32_t)((i * C::NW + wave) * 1024);
+        if (i == 0)
+            dma16_so<true>(srd, lds, s.voff, 0);
+        else
+            dma16_so<false>(srd, lds, s.voff,
+                            __builtin_amdgcn_readfirstlane(i * s.stride));
+    }
+}
+
+// The next K tile of the load stream, ready to issue: buffer resources
+// of its A and B rows from its first K column and its LDS stage.
+struct BulkTile {
+    i32x4 sa, sb;
+    uint32_t lds;
+    bool live;   // the stream has this tile
+};
+
+// Loads of the stream in issue order (owned sub-tensor, K tile).
+template <class C, class P>
+struct BulkCursor {
+    const P &prov;
+    BulkStream sa, sb;
+    int t, kt, nk, total, G;
+    int issued;   // tiles issued so far
+    int wave, lane;
+
+    __device__ __forceinline__ void start(int t0) {
+        const Job j = prov.job(t0);
+        nk = pp_tiles<C>(j.K);
+        // K = 0 takes one tile of zeros: an empty buffer range
+        const bool k0 = j.K == 0;
+        sa = bulk_stream<C>(j.a_row, k0 ? 0 : j.a_rem, j.lda, wave, lane);
+        sb = bulk_stream<C>(j.b_row, k0 ? 0 : j.b_rem, j.ldb, wave, lane);
+    }
+    __device__ BulkCursor(const P &p, int t0, int total_, int G_, int w,
+                          int l)
+        : prov(p), t(t0), kt(0), total(total_), G(G_), issued(0), wave(w),
+          lane(l) {
+        start(t0);
+    }
+    __device__ __forceinline__ BulkTile prepare(char *smem) const {
+        BulkTile T;
+        T.live = t < total;
+        const int64_t skip = (int64_t)kt * C::BK * C::ES;
+        T.sa = make_srd(sa.row + skip, sat_bytes(sa.rem - skip));
+        T.sb = make_srd(sb.row + skip, sat_bytes(sb.rem - skip));
+        T.lds = lds_addr(smem) + (uint32_t)((issued % C::NS) * C::STAGE);
+        return T;
+    }
+    // load r of this wavefront's share of the tile: A blocks first, then B
+    __device__ __forceinline__ void load(const BulkTile &T, int r) const {
+        constexpr int NA = C::BM / C::RPK / C::NW;
+        const bool a = r < NA;
+        const int i = a ? r : r - NA;
+        const uint32_t lds = T.lds + (a ? 0u : (uint32_t)(C::BM * C::RBY)) +
+                             (uint32_t)((i * C::NW + wave) * 1024);
+        const BulkStream &st = a ? sa : sb;
+        if (i == 0)
+            dma16_so<true>(a ? T.sa : T.sb, lds, st.voff, 0);
+        else
+            dma16_so<false>(a ? T.sa : T.sb, lds, st.voff,
+                            __builtin_amdgcn_readfirstlane(i * st.stride));
+    }
+    __device__ __forceinline__ void advance() {
+        ++issued;
+        if (++kt == nk) {
+            kt = 0;
+            t += G;
+            if (t < total) start(t);
+        }
+    }
+    __device__ __forceinline__ void issue(char *smem) {
+        const BulkTile T = prepare(smem);
+        if (!T.live) return;
+#pragma unroll
+        for (int r = 0; r < C::LPW; ++r) load(T, r);
+        advance();
+    }
+};
+
+template <class C>
+struct BulkFrags {
+    i32x4 a[C::BK / 16][C::FM];
+    i32x4 b[C::BK / 16][C::FN];
+};
+
+// Wait until at most the loads of `later` tiles (0 <= later < NS) are
+// outstanding.
+template <class C>
+__device__ __forceinline__ void wait_later(int later) {
+    static_assert(C::NS <= 5, "wait table");
+    switch (later) {
+    case 0: wait_vmem(); break;
+    case 1: wait_vmem_le<C::LPW>(); break;
+    case 2: wait_vmem_le<2 * C::LPW>(); break;
+    case 3: wait_vmem_le<3 * C::LPW>(); break;
+    default: wait_vmem_le<(C::NS - 1) * C::LPW>(); break;
+    }
+}
+
+// Barrier of the bulk-read ring: this wavefront's LDS reads are complete
+// (a wait the compiler sees, so that it knows the fragments read before
+// are in registers and inserts no waits of its own for them), then the
+// workgroup barrier.
+__device__ __forceinline__ void bulk_barrier() {
+    // lgkmcnt(0); vmcnt and expcnt at their no-wait maxima
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4));
+    __builtin_amdgcn_s_barrier();
+}
+
+// One iteration of the bulk-read ring: contract tile q (fragments in cur)
+// and read tile q + 1 into nxt.  The tile's MFMAs are cut into LPW groups;
+// one load of tile q + NS leads each group (with one wavefront per SIMD a
+// load that waits to issue stalls the MFMAs behind it, so the loads are
+// spread over the whole tile period), and the fragment reads of tile
+// q + 1 are slotted one after each MFMA of the first groups.
+template <class C, class P>
+__device__ __forceinline__ void bulk_iter(BulkCursor<C, P> &ld, char *smem,
+                                          int q, int wave, int lane, int wm,
+                                          int wn, const BulkFrags<C> &cur,
+                                          BulkFrags<C> &nxt,
+                                          f32x16 (&acc)[C::FM][C::FN]) {
+    constexpr int KK = C::BK / 16;
+    constexpr int NF = C::FM + C::FN;           // fragments per K step
+    constexpr int NRD = KK * NF;                // fragment reads per tile
+    constexpr int NM = KK * C::FM * C::FN;      // MFMAs per tile
+    constexpr int NG = C::LPW;                  // groups, one load each
+    constexpr int MPG = NM / NG;                // MFMAs per group
+    static_assert(NM % NG == 0 && NRD % MPG == 0 && NRD / MPG <= NG,
+                  "group layout");
+    __builtin_amdgcn_sched_barrier(0);
+    if (q + 1 < ld.issued) wait_later<C>(ld.issued - q - 2);
+    bulk_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    const BulkTile T = ld.prepare(smem);
+    // (a stale stage is read when tile q + 1 does not exist; unused)
+    const char *nst = smem + ((q + 1) % C::NS) * C::STAGE;
+    const int r = lane & 31, half = lane >> 5;
+    const int sw = swz_f<C>(r);
+    const char *Aw = nst + wm * C::TM * C::RBY + r * C::RBY;
+    const char *Bw = nst + C::BM * C::RBY + wn * C::TN * C::RBY + r * C::RBY;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (T.live) ld.load(T, g);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int x = g * MPG; x < (g + 1) * MPG; ++x) {
+            if (x < NRD) {
+                const int kk = x / NF, f = x % NF;
+                const int co = ((2 * kk + half) ^ sw) << 4;
+                if (f < C::FM)
+                    nxt.a[kk][f] = *reinterpret_cast<const i32x4 *>(
+                        Aw + f * 32 * C::RBY + co);
+                else
+                    nxt.b[kk][f - C::FM] = *reinterpret_cast<const i32x4 *>(
+                        Bw + (f - C::FM) * 32 * C::RBY + co);
+            }
+        }
+#pragma unroll
+        for (int x = g * MPG; x < (g + 1) * MPG; ++x) {
+            const int kk = x / (C::FM * C::FN), m = x % (C::FM * C::FN);
+            const int i = m / C::FN, jj = m % C::FN;
+            acc[i][jj] = mfma_bf16(cur.a[kk][i], cur.b[kk][jj], acc[i][jj]);
+        }
+#pragma unroll
+        for (int x = g * MPG; x < (g + 1) * MPG; ++x) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            if (x < NRD) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (T.live) ld.advance();
+}
+
+// Owned sub-tensors one after another; the K tiles of each are taken in
+// pairs (register sets fixed at compile time), an odd last tile moves the
+// next sub-tensor's first fragments back into set 0.
+template <class C, class P>
+__device__ __forceinline__ void run_bulk(const P &prov, char *smem) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
+    const int wm = wave / C::WN, wn = wave % C::WN;
+    const int G = prov.n_prog(), total = prov.count();
+    int t = program_slot(blockIdx.x, G);
+    if (t >= total) return;
+    BulkCursor<C, P> ld(prov, t, total, G, wave, lane);
+    for (int s = 0; s < C::NS; ++s) ld.issue(smem);
+    BulkFrags<C> F0, F1;
+    wait_later<C>(ld.issued - 1);   // tile 0
+    ring_barrier();
+#pragma unroll
+    for (int kk = 0; kk < C::BK / 16; ++kk)
+        read_frags<C>(smem, wm, wn, lane, kk, F0.a[kk], F0.b[kk]);
+    f32x16 acc[C::FM][C::FN];
+    int q = 0;
+    while (true) {
+        const Job j = prov.job(t);
+        const int nk = pp_tiles<C>(j.K);
+        zero_acc<C>(acc);
+        int kt = 0;
+        for (; kt + 2 <= nk; kt += 2, q += 2) {
+            bulk_iter<C, P>(ld, smem, q, wave, lane, wm, wn, F0, F1, acc);
+            bulk_iter<C, P>(ld, smem, q + 1, wave, lane, wm, wn, F1, F0,
+                            acc);
+        }
+        if (kt < nk) {
+            bulk_iter<C, P>(ld, smem, q, wave, lane, wm, wn, F0, F1, acc);
+            ++q;
+            F0 = F1;
+        }
+        epilogue<C>(j, wm, wn, lane, acc, nullptr);
+        t += G;
+        if (t >= total) break;
+    }
+}
+
 // ------------------------------------------------- register-staged ring
 //
 // Staged schedule (bf16, A and B both k-contiguous, 64-deep K tiles): the
@@ -1829,6 +2195,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_tiled_kernel(
         run_pingpong<C>(p, smem);
     else if constexpr (C::STG)
         run_staged<C>(p, smem);
+    else if constexpr (C::BLK)
+        run_bulk<C>(p, smem);
     else if constexpr (C::XT && C::NS == 5)
         run_direct_x5<C>(p, smem);
     else if constexpr (C::HALVES)
@@ -1851,6 +2219,8 @@ __attribute__((amdgpu_waves_per_eu(C::WPE, C::WPE))) void gemm_grouped_kernel(
         run_pingpong<C>(p, smem);
     else if constexpr (C::STG)
         run_staged<C>(p, smem);
+    else if constexpr (C::BLK)
+        run_bulk<C>(p, smem);
     else if constexpr (C::XT && C::NS == 5)
         run_direct_x5<C>(p, smem);
     else if constexpr (C::HALVES)
@@ -1910,6 +2280,10 @@ VariantEntry make_entry() {
     make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, TG_SCHED_CROSS>>(), \
         make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, TG_SCHED_CROSS>>()
 
+#define TG_VARIANTS_BLK(DT, BM, BN, WM, WN, RBY, NS)                          \
+    make_entry<Cfg<DT, BM, BN, WM, WN, true, false, RBY, NS, TG_SCHED_BULK>>(), \
+        make_entry<Cfg<DT, BM, BN, WM, WN, true, true, RBY, NS, TG_SCHED_BULK>>()
+
 #define TG_VARIANTS_STG(DT, BM, BN)                                           \
     make_entry<Cfg<DT, BM, BN, 2, 2, true, false, 128, 2, TG_SCHED_STAGED>>()
 
@@ -1932,6 +2306,8 @@ const VariantEntry *table(int *count) {
         TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_STG(TG_BF16, 256, 256),
+        TG_VARIANTS_BLK(TG_BF16, 256, 256, 2, 2, 64, 4),
+        TG_VARIANTS_BLK(TG_BF16, 256, 256, 2, 4, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 128, 2),
         TG_VARIANTS_FOR(TG_BF16, 64, 64, 2, 2, 128, 2),

@@ -248,16 +248,19 @@ bool skinny_ok(const Problem &p, const tg_in *A, const tg_in *B) {
 
 // First tiled variant matching the request; zero fields match anything.
 // Ping-pong variants have no tail fill for a 16-byte chunk straddling K:
-// pp_ok is false when K is not a multiple of the chunk.  Staged variants
+// pp_ok is false when K is not a multiple of the chunk.  Bulk-read
+// variants need K a whole number of their 32-deep K tiles (k32_ok).  Staged variants
 // need K a whole number of their K tiles (k_tiles_ok: K % 64 == 0 for
 // bf16) and apply no scales.
 int find_variant(int dt, int bm, int bn, int wm, int wn, int bk, int stages,
                  int sched, bool b_nk, bool c_bf16, bool pp_ok,
-                 bool scaled = false, bool k_tiles_ok = false) {
+                 bool scaled = false, bool k_tiles_ok = false,
+                 bool k32_ok = false) {
     int n = tiled_variant_count();
     for (int i = 0; i < n; ++i) {
         const TiledVariant &v = tiled_variant(i);
         if (v.sched == TG_SCHED_PINGPONG && !pp_ok) continue;
+        if (v.sched == TG_SCHED_BULK && !k32_ok) continue;
         if (v.sched == TG_SCHED_STAGED && (scaled || !k_tiles_ok)) continue;
         if (v.dtype == dt && v.bm == bm && v.bn == bn && v.b_nk == b_nk &&
             v.c_bf16 == c_bf16 && (wm == 0 || v.wm == wm) &&
@@ -375,7 +378,8 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
                                        cfg.wn, cfg.bk, cfg.stages, cfg.sched,
                                        p.b_nk, p.c_bf16,
                                        chunk_multiple(L.Kc, L.gemm_dt),
-                                       p.scaled, L.Kc % 64 == 0) >= 0))
+                                       p.scaled, L.Kc % 64 == 0,
+                                       L.Kc % 32 == 0) >= 0))
             cfg.kind = TG_KIND_TILED;
         else
             cfg.kind = TG_KIND_SIMPLE;
@@ -469,7 +473,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         L.variant = find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
                                  cfg.bk, cfg.stages, cfg.sched, p.b_nk,
                                  p.c_bf16, chunk_multiple(L.Kc, L.gemm_dt),
-                                 p.scaled, L.Kc % 64 == 0);
+                                 p.scaled, L.Kc % 64 == 0, L.Kc % 32 == 0);
         if (L.variant < 0)
             return fail(TG_E_UNSUPPORTED,
                         "no tiled kernel for dtype %d, %d x %d, waves %d x %d,"
@@ -1115,14 +1119,15 @@ tg_status tile_gemm_grouped_prepare(int32_t n, const tg_in *A,
         for (auto &p : ps) work += p.M * p.N;
         cfg.bm = cfg.bn = work >= (int64_t)256 * 256 * 256 ? 256 : 128;
     }
-    bool pp_ok = true, tiles_ok = true;
+    bool pp_ok = true, tiles_ok = true, k32_ok = true;
     for (auto &p : ps) {
         pp_ok = pp_ok && chunk_multiple(p.K, TG_BF16);
         tiles_ok = tiles_ok && p.K % 64 == 0;
+        k32_ok = k32_ok && p.K % 32 == 0;
     }
     int variant = find_variant(TG_BF16, cfg.bm, cfg.bn, cfg.wm, cfg.wn,
                                cfg.bk, cfg.stages, cfg.sched, b_nk == 1,
-                               c_bf16 == 1, pp_ok, false, tiles_ok);
+                               c_bf16 == 1, pp_ok, false, tiles_ok, k32_ok);
     if (variant < 0)
         return fail(TG_E_UNSUPPORTED, "no tiled kernel %d x %d", cfg.bm,
                     cfg.bn);

@@ -536,13 +536,23 @@ def test_grouped_matches_oracle_and_single_launches():
             assert torch.equal(c, e), rep
 
 
+GROUPED_SHAPES = {
+    # K tails shorter than a K tile
+    "ragged_k": [(1, 264, 200), (300, 384, 72), (520, 136, 328),
+                 (4352, 256, 136), (130, 1040, 64)],
+    # every K a multiple of 32 (also runs the bulk-read configurations)
+    "k32": [(1, 264, 96), (300, 384, 32), (520, 136, 320), (4352, 256, 160),
+            (130, 1040, 64)],
+}
+
+
 @pytest.mark.parametrize("b_trans", [False, True])
-def test_every_grouped_configuration(b_trans):
-    """Every tiled configuration of a grouped launch (K tails shorter than a
-    K tile, ragged M and N, several sub-tensors per program) matches the
-    oracle and the single launches of the same configuration bitwise."""
-    shapes = [(1, 264, 200), (300, 384, 72), (520, 136, 328),
-              (4352, 256, 136), (130, 1040, 64)]
+@pytest.mark.parametrize("batch", sorted(GROUPED_SHAPES))
+def test_every_grouped_configuration(b_trans, batch):
+    """Every tiled configuration of a grouped launch (ragged M and N,
+    several sub-tensors per program) matches the oracle and the single
+    launches of the same configuration bitwise."""
+    shapes = GROUPED_SHAPES[batch]
     note("every grouped", b_trans, shapes)
     As = [dev(synth.to_bf16(synth.normal((m, k), 120 + i)))
           for i, (m, n, k) in enumerate(shapes)]
@@ -764,10 +774,13 @@ def _pick(C, rows):
 # straddling K is filled element by element, in the first and in a later
 # hand-over); and a grid of more sub-tensors than persistent programs, so
 # that programs own several each (the K-tile stream crosses sub-tensor
-# boundaries).
+# boundaries).  K a multiple of 32 (an odd and an even number of 32-deep
+# tiles, one tile, several sub-tensors per program) reaches the bulk-read
+# configurations as well.
 EVERY_SHAPES = [(300, 264, 136), (520, 600, 328), (200, 136, 0),
                 (4352, 4352, 72), (300, 264, 101), (520, 136, 77),
-                (130, 264, 37)]
+                (130, 264, 37), (300, 264, 160), (520, 136, 64),
+                (130, 264, 32), (4352, 4352, 96)]
 
 
 @pytest.mark.parametrize("b_trans", [False, True])
