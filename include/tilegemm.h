@@ -138,11 +138,17 @@ typedef enum tg_sched {
                               ahead and stored into a two-stage LDS ring
                               (bf16, B stored N x K, binary32 output, no
                               scales, K a multiple of 64)                   */
-    TG_SCHED_BULK = 5      /* four wavefronts of 128 x 128 outputs; each K
+    TG_SCHED_BULK = 5,     /* four wavefronts of 128 x 128 outputs (or
+                              eight of 128 x 64); each K
                               tile's fragments read from LDS into registers
                               in one burst a tile period ahead, freeing its
                               stage for loads NS - 1 tiles ahead (bf16, B
-                              stored N x K, K a multiple of 16 bytes)       */
+                              stored N x K, K a multiple of 32)             */
+    TG_SCHED_CROSS_WARM = 6 /* the cross-tile schedule (two stages, B stored
+                              N x K, bf16) touching the L2 lines of the K
+                              tile two tiles beyond the one being loaded,
+                              so that its direct loads hit the L2 where the
+                              operands stream from HBM (long K)             */
 } tg_sched;
 
 typedef struct tg_config {
@@ -495,7 +501,8 @@ tg_status tile_tune_cache_load(const char *path);
  * and ksplit; log2 of the sub-tensor count, of the program count and of
  * the sub-tensors per program; the fraction of the last round of
  * sub-tensors that has work; the useful fraction of the padded output
- * area; flags for the ping-pong and the cross-tile schedule; log2 splitk;
+ * area; a flag for the ping-pong schedule; 1 for the cross-tile schedule,
+ * 2 for the cross-tile schedule with the L2 warm-up, else 0; log2 splitk;
  * a flag for the configuration the fixed heuristic would pick.
  * tile_picker_set installs a cost model (host copy of the parameters in the
  * layout of tile_mlp_*, with per-feature mean and standard deviation used

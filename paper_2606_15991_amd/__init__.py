@@ -33,7 +33,7 @@ TG_PREC_NATIVE, TG_PREC_BF16X3, TG_PREC_BF16X6 = 0, 1, 2
 TG_KIND_AUTO, TG_KIND_TILED, TG_KIND_SKINNY, TG_KIND_SIMPLE = 0, 1, 2, 3
 # tg_sched
 TG_SCHED_ANY, TG_SCHED_LOCKSTEP, TG_SCHED_PINGPONG, TG_SCHED_CROSS, \
-    TG_SCHED_STAGED, TG_SCHED_BULK = 0, 1, 2, 3, 4, 5
+    TG_SCHED_STAGED, TG_SCHED_BULK, TG_SCHED_CROSS_WARM = 0, 1, 2, 3, 4, 5, 6
 TG_ERROR_NORM_DOUBLES = 514
 
 PRECISIONS = {"native": TG_PREC_NATIVE, "bf16x3": TG_PREC_BF16X3,

@@ -71,7 +71,10 @@ struct Cfg {
     static constexpr int NS = NS_;              // LDS stages in the ring
     static constexpr int SCHED = SCH_;          // wavefront schedule
     static constexpr bool PP = SCH_ == TG_SCHED_PINGPONG;
-    static constexpr bool XT = SCH_ == TG_SCHED_CROSS;
+    static constexpr bool XT =
+        SCH_ == TG_SCHED_CROSS || SCH_ == TG_SCHED_CROSS_WARM;
+    // cross-tile schedule with an L2 warm-up of later K tiles
+    static constexpr bool WARM = SCH_ == TG_SCHED_CROSS_WARM;
     static constexpr bool STG = SCH_ == TG_SCHED_STAGED;
     static constexpr bool BLK = SCH_ == TG_SCHED_BULK;
     static constexpr int BK = RBY / ES;         // K elements per K tile
@@ -97,9 +100,9 @@ struct Cfg {
     static constexpr int SCALE_SLOT = (BM + BN) * 4;
     static constexpr int NSLOT = NS + 1;
     static constexpr int SMEM =
-        (SCH_ == TG_SCHED_CROSS && NS == 3 ? 5 * (STAGE / 2) : NS * STAGE) +
-        (SCH_ == TG_SCHED_CROSS && NS == 2 ? 256 : 0) +
-        (DIRECT && SCH_ != TG_SCHED_CROSS && SCH_ != TG_SCHED_STAGED &&
+        (XT && NS == 3 ? 5 * (STAGE / 2) : NS * STAGE) +
+        (WARM ? 256 : 0) +
+        (DIRECT && !XT && SCH_ != TG_SCHED_STAGED &&
                  SCH_ != TG_SCHED_BULK
              ? NSLOT * SCALE_SLOT
              : 0);
@@ -107,15 +110,15 @@ struct Cfg {
     static_assert(TM % 32 == 0 && TN % 32 == 0, "wave tile");
     static_assert(RBY == 128 || RBY == 64, "K-tile row bytes");
     static_assert(NS == 2 || NS == 4 ||
-                      (NS == 5 && SCH_ == TG_SCHED_CROSS && RBY == 64) ||
+                      (NS == 5 && XT && !WARM && RBY == 64) ||
                       (NS == 5 && SCH_ == TG_SCHED_BULK) ||
-                      (NS == 3 && SCH_ == TG_SCHED_CROSS && RBY == 128 &&
+                      (NS == 3 && XT && !WARM && RBY == 128 &&
                        BM == BN),
                   "ring of 2 or 4 stages, 5 of 64-byte rows, or 5 operand "
                   "halves (NS = 3)");
     // NS = 3 with the cross-tile schedule: the LDS holds five operand
     // tiles (A or B of one K tile each) instead of three whole stages.
-    static constexpr bool HALVES = SCH_ == TG_SCHED_CROSS && NS == 3;
+    static constexpr bool HALVES = XT && NS == 3;
     static_assert(DIRECT || (RBY == 128 && NS == 2), "f32 register path");
     static_assert((BM / RPK) % NW == 0, "A 1 KiB blocks per wave");
     static_assert(B_KMAJOR ? (BK * RB / 1024) % NW == 0
@@ -138,6 +141,8 @@ struct Cfg {
                   "ping-pong: two groups of four wavefronts, >= 3 stages");
     static_assert(!XT || (DIRECT && DT == TG_BF16 && (BK / 16) % 2 == 0),
                   "cross-tile schedule: bf16, even number of K steps");
+    static_assert(!WARM || (NS == 2 && BNK && DT == TG_BF16),
+                  "L2 warm-up: two-stage cross-tile ring, B stored N x K");
     static_assert(!BLK || (DT == TG_BF16 && BNK && NS >= 4 &&
                            BK / 16 * (FM + FN) * 4 <= 128),
                   "bulk schedule: bf16, B stored N x K, a ring of at least "
@@ -978,10 +983,6 @@ __device__ __forceinline__ void mfma_step(const i32x4 (&af)[C::FM],
 }
 
 
-#ifndef TG_L2_PF
-#define TG_L2_PF 0
-#endif
-
 // L2 warm-up of K tile k0 of one owned sub-tensor (B stored N x K): each
 // lane touches one 64-byte half of one 128-byte row segment with a 4-byte
 // load into a scratch LDS word that nothing reads, so the direct loads
@@ -989,7 +990,11 @@ __device__ __forceinline__ void mfma_step(const i32x4 (&af)[C::FM],
 // 8 x 4 block of sub-tensors on each XCD, so a program touches only the A
 // rows whose index is tn mod 4 and the B rows whose index is tm mod 8:
 // together the block's programs touch each line once.  Two instructions
-// per wavefront.
+// per wavefront.  Where the operands stream from HBM (long K, operands
+// larger than the last-level cache) the direct loads of a tile then see
+// L2 latency instead of HBM latency; where they already hit the MALL the
+// extra requests cost more than they save, so this is a configuration
+// of its own.
 template <class C>
 __device__ __forceinline__ void warm_l2(const Job &j, int k0, char *dummy,
                                         int wave, int lane) {
@@ -1029,7 +1034,9 @@ template <class C, class P>
 __device__ __forceinline__ void run_direct_xt(const P &prov, char *smem) {
     constexpr int KK = C::BK / 16;                 // K steps per tile (even)
     constexpr int NR = C::FM + (C::B_KMAJOR ? 2 : 1) * C::FN;
-    constexpr int PF = (C::NS == 2 && !C::B_KMAJOR) ? TG_L2_PF : 0;
+    // warm-up distance: tile pend_b + PF is touched when pend_b's B loads
+    // are issued, two tile periods before its own direct loads
+    constexpr int PF = C::WARM ? 2 : 0;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform
@@ -2276,6 +2283,12 @@ VariantEntry make_entry() {
     make_entry<Cfg<DT, BM, BN, 2, 4, true, false, RBY, NS, TG_SCHED_CROSS>>(), \
         make_entry<Cfg<DT, BM, BN, 2, 4, true, true, RBY, NS, TG_SCHED_CROSS>>()
 
+#define TG_VARIANTS_XW_NK(DT, BM, BN)                                         \
+    make_entry<Cfg<DT, BM, BN, 2, 4, true, false, 128, 2,                      \
+                   TG_SCHED_CROSS_WARM>>(),                                    \
+        make_entry<Cfg<DT, BM, BN, 2, 4, true, true, 128, 2,                   \
+                       TG_SCHED_CROSS_WARM>>()
+
 #define TG_VARIANTS_XT_KN(DT, BM, BN, RBY, NS)                                \
     make_entry<Cfg<DT, BM, BN, 2, 4, false, false, RBY, NS, TG_SCHED_CROSS>>(), \
         make_entry<Cfg<DT, BM, BN, 2, 4, false, true, RBY, NS, TG_SCHED_CROSS>>()
@@ -2306,6 +2319,7 @@ const VariantEntry *table(int *count) {
         TG_VARIANTS_XT_NK(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_XT_KN(TG_BF16, 256, 256, 64, 5),
         TG_VARIANTS_STG(TG_BF16, 256, 256),
+        TG_VARIANTS_XW_NK(TG_BF16, 256, 256),
         TG_VARIANTS_BLK(TG_BF16, 256, 256, 2, 2, 64, 4),
         TG_VARIANTS_BLK(TG_BF16, 256, 256, 2, 4, 64, 4),
         TG_VARIANTS_FOR(TG_BF16, 128, 128, 2, 2, 64, 4),

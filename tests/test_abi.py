@@ -350,7 +350,8 @@ def test_picker_features_describe_the_configuration():
                 np.log2(n_prog), np.log2(rounds),
                 tiles / (n_prog * rounds), 1.0,
                 1.0 if cfg["sched"] == tg.TG_SCHED_PINGPONG else 0.0,
-                1.0 if cfg["sched"] == tg.TG_SCHED_CROSS else 0.0,
+                {tg.TG_SCHED_CROSS: 1.0,
+                 tg.TG_SCHED_CROSS_WARM: 2.0}.get(cfg["sched"], 0.0),
                 np.log2(max(cfg["splitk"], 1)),
                 1.0 if cfg == dflt else 0.0]
         assert np.allclose(f, want, rtol=0, atol=1e-6), (cfg, f)
@@ -483,3 +484,24 @@ def test_bench_traffic_only_for_the_profiled_sources(monkeypatch):
     assert bench.traffic_from_profile() == nbytes
     monkeypatch.setattr(bench, "kernel_source_sha", lambda: "0" * 64)
     assert bench.traffic_from_profile() is None
+
+
+def test_long_k_default_takes_the_l2_warm_up():
+    """The fixed heuristic picks the cross-tile schedule with the L2
+    warm-up for bf16 products with long K (at least 16384 and twice the
+    larger of M and N, B stored N x K) and the plain cross-tile schedule
+    otherwise."""
+    old = tg.tile_picker_mode(0)
+    try:
+        for M, N, K, want in ((8192, 8192, 8192, tg.TG_SCHED_CROSS),
+                              (8192, 4096, 16384, tg.TG_SCHED_CROSS_WARM),
+                              (4096, 4096, 32768, tg.TG_SCHED_CROSS_WARM),
+                              (8192, 8192, 12288, tg.TG_SCHED_CROSS)):
+            A = torch.empty((M, K), dtype=torch.bfloat16)
+            B = torch.empty((N, K), dtype=torch.bfloat16)
+            C = torch.empty((M, N), dtype=torch.float32)
+            cfg = tg.tile_gemm_plan(A, B, C, b_trans=True,
+                                    want_map=False)[0]
+            assert cfg["sched"] == want, (M, N, K, cfg)
+    finally:
+        tg.tile_picker_mode(old)
