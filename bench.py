@@ -153,9 +153,12 @@ def bench_bf16_main(args, tg):
     Bt = synth.to_bf16(synth.normal((N, K), 202))   # B^T, row-major
     Ad, Bd = A.cuda(), Bt.cuda()
     C = torch.empty((M, N), device="cuda")
+    # launch configuration: the library's default, or the one given with
+    # --config (profiling of other schedules on the same workload)
+    cfg = json.loads(args.config) if args.config else None
 
     def step():
-        tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True)
+        tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True, config=cfg)
 
     # clock settling: back-to-back launches for --settle-ms of wall time
     # before the warm-up (after start-up the power manager first lowers the
@@ -185,7 +188,8 @@ def bench_bf16_main(args, tg):
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(s)
             h0 = time.perf_counter()
-            tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True, checked=checked)
+            tg.tile_gemm(Ad, Bd, C, 256, 256, b_trans=True, checked=checked,
+                         config=cfg)
             host_us[checked].append((time.perf_counter() - h0) * 1e6)
             e1.record(s)
             e1.synchronize()
@@ -685,6 +689,9 @@ def main():
     ap.add_argument("--settle-ms", type=float, default=1000.0,
                     help="wall time of back-to-back headline launches "
                          "before the warm-up (clock settling)")
+    ap.add_argument("--config", default=None,
+                    help="with --quick: JSON launch configuration of the "
+                         "headline product (default: the library's choice)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter scaling)")
     ap.add_argument("--decode", action="store_true",
@@ -708,6 +715,10 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not "
               "supported: the benchmark runs on a single GPU", file=sys.stderr)
+        sys.exit(2)
+    if args.config and not args.quick:
+        print("--config applies to the headline launch of a --quick run",
+              file=sys.stderr)
         sys.exit(2)
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -782,11 +793,15 @@ def main():
                                "f32 accumulate+output, C partition 256x256, "
                                "A row-major, B column-major (stored N x K)",
                    "M": 8192, "N": 8192, "K": 8192,
-                   "partition": [256, 256], "parallelism": "none"},
+                   "partition": [256, 256], "parallelism": "none",
+                   **({"launch_config": json.loads(args.config)}
+                      if args.config else {})},
         "roofline": {"bound": "mfma", "achieved": round(tflops, 2),
                      "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
                      "frac": round(tflops / PEAK_TFLOPS["bf16"], 4),
-                     "traffic": traffic_from_profile()},
+                     # the committed counters describe the default launch
+                     "traffic": None if args.config
+                     else traffic_from_profile()},
         "clock": res["clock"],
         "err_rel_fro": err,
         "err_rows": nrows,
