@@ -508,15 +508,38 @@ def bench_decode_layer(args, tg, d=5120, layers=16):
                                     workspace=wsf, stream=stream)
             tg.tile_add(h, q, res, checked=False, stream=stream)
             h = res
+    # the residual add folded into the product's store (the program that
+    # owns an element of the layer output adds the layer input to it)
+    def run_res(stream=None):
+        h = xs
+        for i in range(layers):
+            norm, q, res = bufs[3 * i:3 * i + 3]
+            tg.tile_rms_norm(h, nw, norm, 1e-6, checked=False, stream=stream)
+            tg.tile_gemm(norm, Ws[i], res, b_trans=True, checked=False,
+                         workspace=ws, residual=h, stream=stream)
+            h = res
+
+    def run_fused_res(stream=None):
+        h = xs
+        for i in range(layers):
+            norm, q, res = bufs[3 * i:3 * i + 3]
+            tg.tile_rms_norm_matvec(h, nw, Ws[i], res, 1e-6, checked=False,
+                                    workspace=wsf, residual=h, stream=stream)
+            h = res
     ms_eager = timed(run, 20, 5)
     ms_graph = graph_ms([lambda st: run(stream=st)], reps=20)
     ms_fused = graph_ms([lambda st: run_fused(stream=st)], reps=20)
+    ms_res = graph_ms([lambda st: run_res(stream=st)], reps=20)
+    ms_fused_res = graph_ms([lambda st: run_fused_res(stream=st)], reps=20)
     wbytes = 2.0 * d * d
     out = {"d": d, "layers": layers,
            "us_per_layer_eager": ms_eager * 1e3 / layers,
            "us_per_layer_graph": ms_graph * 1e3 / layers,
            "weight_gbs_graph": wbytes * layers / (ms_graph * 1e-3) / 1e9,
-           "us_per_layer_graph_fused_norm": ms_fused * 1e3 / layers}
+           "us_per_layer_graph_fused_norm": ms_fused * 1e3 / layers,
+           "us_per_layer_graph_residual_folded": ms_res * 1e3 / layers,
+           "us_per_layer_graph_fused_norm_residual_folded":
+               ms_fused_res * 1e3 / layers}
     log("decode layer", out)
     return out
 

@@ -189,6 +189,19 @@ typedef struct tg_opts {
                              store adds 1 to its element's counter, so a
                              correct launch leaves every counter at 1 more
                              than the caller's initial value               */
+    const tg_in *residual; /* host descriptor of a device M x N residual R
+                             (bf16 or f32, row-major, trans 0), or NULL.
+                             Decode products (TG_KIND_SKINNY, and
+                             tile_rms_norm_matvec) then store C = (product)
+                             + R, the binary32 sum rounded once to C's type:
+                             the residual add of the decode layer (Sec. 3.2,
+                             graph-scope listing) done by the program that
+                             owns each element of C.  R is an immutable
+                             input: sharing bytes with C is TG_E_ALIAS (on
+                             checked launches; with a split over programs
+                             the workspace may not share bytes with it
+                             either).  Other kernel kinds return
+                             TG_E_UNSUPPORTED.                             */
 } tg_opts;
 
 /*

@@ -33,6 +33,10 @@ What it computes (arxiv 2606.15991):
     graph-scope listing, y = x * w / sqrt(mean(x^2) + eps) per row, in
     binary64 (the usual RMSNorm definition; the paper names the operation
     and its eps without writing the formula out).
+  * residual_add -- the residual add that closes the decode layer of
+    Sec. 3.2's graph-scope listing (layer output = matvec result + layer
+    input), applied to a finished binary64 product: scales belong to the
+    product, the residual is added unscaled, the sum is stored once.
   * mlp (submodule) -- binary64 forward/backward of the tile-picker MLP and
     its Adam update.
 """
@@ -264,3 +268,11 @@ def rms_norm_matvec(x, nw, W, eps: float, sw=None) -> np.ndarray:
     xw = decode_bf16(round_bf16(x * nw))
     s = 1.0 / np.sqrt(np.mean(x * x, axis=1) + float(eps))
     return gemm(xw, W, b_nk=True, sa=s, sb=sw)
+
+
+def residual_add(P, R) -> np.ndarray:
+    """out = P + R in binary64: the decode layer's residual add (Sec. 3.2,
+    graph-scope listing) on a finished product P (scales already applied to
+    P; the residual R is added as it is).  Rounding the result to the
+    output format is the caller's one rounding."""
+    return np.asarray(P, dtype=np.float64) + np.asarray(R, dtype=np.float64)

@@ -72,7 +72,8 @@ class tg_opts(ctypes.Structure):
                 ("config", ctypes.POINTER(tg_config)),
                 ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t),
-                ("write_count", ctypes.c_void_p)]
+                ("write_count", ctypes.c_void_p),
+                ("residual", ctypes.POINTER(tg_in))]
 
 
 class tg_grouped_plan(ctypes.Structure):
@@ -273,7 +274,7 @@ def _ptr(t):
 
 
 def make_opts(precision="native", scale_a=None, scale_b=None, config=None,
-              workspace=None, write_count=None, checked=True):
+              workspace=None, write_count=None, checked=True, residual=None):
     o = tg_opts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) \
         else int(precision)
@@ -287,13 +288,18 @@ def make_opts(precision="native", scale_a=None, scale_b=None, config=None,
         o.workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
     o.write_count = _ptr(write_count)
+    if residual is not None:
+        r = make_in(residual)
+        o._res = r  # keep alive
+        o.residual = ctypes.pointer(r)
     return o
 
 
 def tile_gemm(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
               scale_a=None, scale_b=None, config=None, workspace=None,
-              write_count=None, checked=True, stream=None):
-    """C = diag(scale_a) A B diag(scale_b) into C's bm x bn partition.
+              write_count=None, checked=True, residual=None, stream=None):
+    """C = diag(scale_a) A B diag(scale_b) (+ residual, decode products only)
+    into C's bm x bn partition.
 
     B is K x N, or the stored N x K matrix when b_trans.  BF16x3/x6 and
     decode products split along K over several programs need a workspace
@@ -302,7 +308,7 @@ def tile_gemm(A, B, C, bm=0, bn=0, *, b_trans=False, precision="native",
     da, db = make_in(A), make_in(B, b_trans)
     dc = make_out(C, bm, bn)
     o = make_opts(precision, scale_a, scale_b, config, workspace, write_count,
-                  checked)
+                  checked, residual)
     if workspace is None:
         need = lib.tile_gemm_workspace_size(da, db, dc, o)
         if need:
@@ -320,14 +326,14 @@ TG_NOALLOC_SCRATCH_BYTES = 8 << 20
 def tile_gemm_noalloc(A, B, C, bm=0, bn=0, *, b_trans=False,
                       precision="native", scale_a=None, scale_b=None,
                       config=None, write_count=None, checked=True,
-                      stream=None):
+                      residual=None, stream=None):
     """tile_gemm without any device allocation: where tile_gemm takes a
     workspace the library's own per-device scratch is used (calls that
     overlap on one device race on it).  Returns (A, B, C)."""
     da, db = make_in(A), make_in(B, b_trans)
     dc = make_out(C, bm, bn)
     o = make_opts(precision, scale_a, scale_b, config, None, write_count,
-                  checked)
+                  checked, residual)
     _raise(lib.tile_gemm_noalloc(da, db, dc, o, _stream(stream)))
     tile_gemm_noalloc.last_partition = (dc.bm, dc.bn)
     return A, B, C
@@ -376,9 +382,10 @@ def tile_rms_norm_matvec_workspace_size(x, W, y) -> int:
 
 def tile_rms_norm_matvec(x, nw, W, y, eps=1e-6, *, scale_w=None,
                          checked=True, write_count=None, workspace=None,
-                         stream=None):
-    """y = rms_norm(x; nw, eps) . W^T with the normalisation fused into the
-    decode product (x: M x K bf16, M <= 16; nw: K bf16; W stored N x K).
+                         residual=None, stream=None):
+    """y = rms_norm(x; nw, eps) . W^T (+ residual) with the normalisation
+    fused into the decode product (x: M x K bf16, M <= 16; nw: K bf16; W
+    stored N x K).
     The workspace of a K split over programs is allocated here from torch
     when not given (workspace=False: no split).  Returns y."""
     if nw.dim() == 1:
@@ -391,7 +398,7 @@ def tile_rms_norm_matvec(x, nw, W, y, eps=1e-6, *, scale_w=None,
     elif workspace is False:
         workspace = None
     o = make_opts(scale_b=scale_w, write_count=write_count, checked=checked,
-                  workspace=workspace)
+                  workspace=workspace, residual=residual)
     _raise(lib.tile_rms_norm_matvec(make_in(x), make_in(nw), float(eps),
                                     make_in(W, True), dy, o, _stream(stream)))
     tile_rms_norm_matvec.last_partition = (dy.bm, dy.bn)

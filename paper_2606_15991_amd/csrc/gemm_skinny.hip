@@ -48,6 +48,15 @@ __device__ __forceinline__ uint4 ld_chunk(const char *row, int k, int K,
     return uint4{0, 0, 0, 0};
 }
 
+// Residual element (m, n), as binary32.
+__device__ __forceinline__ float residual_at(const SkinnyArgs &g, int m,
+                                             int n) {
+    const int64_t off = (int64_t)m * g.ldr + n;
+    return g.res_bf16
+               ? bf16_bits_to_f32(static_cast<const uint16_t *>(g.res)[off])
+               : static_cast<const float *>(g.res)[off];
+}
+
 // NORM: the activation rows are RMS-normalised on the fly (the normalisation
 // step of the decode layer fused into the product): each activation chunk
 // is multiplied by the matching chunk of the normalisation weights nw and
@@ -293,6 +302,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             if (n < g.N) {
                 float y = s[v] * sa;
                 if (g.scale_w) y *= g.scale_w[n];
+                if (g.res) y += residual_at(g, m, n);
                 int64_t off = (int64_t)m * g.ldy + n;
                 if constexpr (CBF16)
                     static_cast<uint16_t *>(g.y)[off] = f32_to_bf16_bits(y);
@@ -317,7 +327,8 @@ __global__ __launch_bounds__(KS * 64) void gemm_skinny_norm_kernel(
 
 // Merge of a split product: program p owns sub-tensor p of y (M rows x bn
 // columns); its threads take the sub-tensor's elements in row-major order
-// and sum the splitk partial values of each in split order.
+// and sum the splitk partial values of each in split order, then apply the
+// scales and add the residual.
 template <bool CBF16, bool NORM>
 __global__ __launch_bounds__(256) void skinny_merge_kernel(SkinnyArgs g,
                                                            float eps) {
@@ -337,6 +348,7 @@ __global__ __launch_bounds__(256) void skinny_merge_kernel(SkinnyArgs g,
         }
         float y = v * sa;
         if (g.scale_w) y *= g.scale_w[n];
+        if (g.res) y += residual_at(g, m, n);
         const int64_t off = (int64_t)m * g.ldy + n;
         if constexpr (CBF16)
             static_cast<uint16_t *>(g.y)[off] = f32_to_bf16_bits(y);

@@ -119,6 +119,11 @@ struct SkinnyArgs {
     int32_t steps_per_split;
     float *part;
     float *ssq_part;
+    // residual R (M x N, leading dimension ldr, bf16 when res_bf16) added
+    // to every output before its one rounding, or nullptr
+    const void *res;
+    int64_t ldr;
+    int32_t res_bf16;
 };
 hipError_t launch_skinny(int w_dtype, int c_bf16, int bn, int ksplit,
                          const SkinnyArgs &a, hipStream_t st);

@@ -808,6 +808,30 @@ tg_status check_split_ws(const tg_opts *o, const Problem &p, int splitk,
     return TG_OK;
 }
 
+// The residual of a decode product (opts->residual): an M x N bf16 or f32
+// row-major device matrix, aligned to its element size.  Fills the kernel
+// arguments (res = nullptr without one).
+tg_status take_residual(const tg_opts *o, const Problem &p, SkinnyArgs &a) {
+    a.res = nullptr;
+    a.ldr = 0;
+    a.res_bf16 = 0;
+    if (!o || !o->residual) return TG_OK;
+    const tg_in *r = o->residual;
+    tg_status st = check_in(r, "residual");
+    if (st != TG_OK) return st;
+    if (r->dtype != TG_BF16 && r->dtype != TG_F32)
+        return fail(TG_E_DTYPE, "residual must be bf16 or f32");
+    if (r->trans || r->rows != p.M || r->cols != p.N)
+        return fail(TG_E_SHAPE, "residual must be %lld x %lld, row-major",
+                    (long long)p.M, (long long)p.N);
+    if ((uintptr_t)r->data % (uintptr_t)esize(r->dtype))
+        return fail(TG_E_SHAPE, "residual not aligned to its element size");
+    a.res = r->data;
+    a.ldr = r->ld;
+    a.res_bf16 = r->dtype == TG_BF16;
+    return TG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -898,16 +922,21 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
     Launch L;
     const size_t have = o && o->workspace ? o->workspace_bytes : 0;
     if ((st = choose(p, A, B, C, o, L, have)) != TG_OK) return st;
+    const bool residual = o && o->residual;
+    if (residual && L.cfg.kind != TG_KIND_SKINNY)
+        return fail(TG_E_UNSUPPORTED, "a residual is added by the decode "
+                                      "kernel only (M <= 16, W stored N x K)");
     const bool checked = !o || o->checked;
     if (checked) {
         // the program map the kernel will walk must be injective and cover
-        // the partition of C, and C may not alias A or B
+        // the partition of C, and C may not alias A, B or the residual
         if ((st = check_launch_map(L)) != TG_OK) return st;
         tg_out part = *C;
         part.bm = L.cfg.bm;
         part.bn = L.cfg.bn;
-        tg_in ins[2] = {*A, *B};
-        if ((st = check_alias(ins, 2, &part)) != TG_OK) return st;
+        tg_in ins[3] = {*A, *B, residual ? *o->residual : *A};
+        if ((st = check_alias(ins, residual ? 3 : 2, &part)) != TG_OK)
+            return st;
     }
     C->bm = L.cfg.bm;
     C->bn = L.cfg.bn;
@@ -929,10 +958,11 @@ tg_status tile_gemm(const tg_in *A, const tg_in *B, tg_out *C,
         a.steps_per_split = L.sps;
         a.part = nullptr;
         a.ssq_part = nullptr;
+        if ((st = take_residual(o, p, a)) != TG_OK) return st;
         if (a.splitk > 1) {
-            const tg_in ins[2] = {*A, *B};
-            if ((st = check_split_ws(o, p, a.splitk, false, ins, 2, C)) !=
-                TG_OK)
+            const tg_in ins[3] = {*A, *B, residual ? *o->residual : *A};
+            if ((st = check_split_ws(o, p, a.splitk, false, ins,
+                                     residual ? 3 : 2, C)) != TG_OK)
                 return st;
             a.part = static_cast<float *>(o->workspace);
         }
@@ -1242,13 +1272,15 @@ tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
         return fail(TG_E_SHAPE, "nw must be 16-byte aligned");
     Launch L;
     if ((st = choose(p, x, W, y, &oo, L, have, true)) != TG_OK) return st;
+    const bool residual = oo.residual != nullptr;
     if (oo.checked) {
         if ((st = check_launch_map(L)) != TG_OK) return st;
         tg_out part = *y;
         part.bm = L.cfg.bm;
         part.bn = L.cfg.bn;
-        tg_in ins[3] = {*x, *W, *nw};
-        if ((st = check_alias(ins, 3, &part)) != TG_OK) return st;
+        tg_in ins[4] = {*x, *W, *nw, residual ? *oo.residual : *x};
+        if ((st = check_alias(ins, residual ? 4 : 3, &part)) != TG_OK)
+            return st;
     }
     y->bm = L.cfg.bm;
     y->bn = L.cfg.bn;
@@ -1266,10 +1298,11 @@ tg_status tile_rms_norm_matvec(const tg_in *x, const tg_in *nw, float eps,
     a.s.ssq_part = nullptr;
     a.norm_w = nw->data;
     a.eps = eps;
+    if ((st = take_residual(&oo, p, a.s)) != TG_OK) return st;
     if (a.s.splitk > 1) {
-        const tg_in ins[3] = {*x, *W, *nw};
-        if ((st = check_split_ws(&oo, p, a.s.splitk, true, ins, 3, y)) !=
-            TG_OK)
+        const tg_in ins[4] = {*x, *W, *nw, residual ? *oo.residual : *x};
+        if ((st = check_split_ws(&oo, p, a.s.splitk, true, ins,
+                                 residual ? 4 : 3, y)) != TG_OK)
             return st;
         char *ws = static_cast<char *>(oo.workspace);
         a.s.part = reinterpret_cast<float *>(ws);

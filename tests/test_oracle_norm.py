@@ -154,3 +154,28 @@ def test_planted_fused_scale_inside_rounding_fails(monkeypatch):
     monkeypatch.setattr(oracle, "rms_norm_matvec", bad)
     with pytest.raises(AssertionError):
         test_fused_norm_matvec_worked_rounding_example()
+
+
+def test_residual_add_closes_the_layer():
+    """The decode layer's output is its matvec result plus its input: with
+    zero weights the layer returns the residual exactly, with a zero
+    residual it returns the product, and scales act on the product only
+    (W = I, output scales 2, residual 1: y = 2 x + 1, not 2 (x + 1))."""
+    rng = np.random.default_rng(14)
+    x = rng.integers(-8, 9, (3, 6)).astype(np.float64)
+    R = rng.integers(-8, 9, (3, 6)).astype(np.float64)
+    P0 = oracle.gemm(x, np.zeros((6, 6)), b_nk=True)
+    assert np.array_equal(oracle.residual_add(P0, R), R)
+    P = oracle.gemm(x, np.eye(6), b_nk=True, sb=np.full(6, 2.0))
+    assert np.array_equal(oracle.residual_add(P, np.zeros((3, 6))), 2 * x)
+    assert np.array_equal(oracle.residual_add(P, np.ones((3, 6))),
+                          2 * x + 1)
+
+
+def test_planted_scaled_residual_fails(monkeypatch):
+    """Scaling the residual with the product (planted) fails the pin."""
+    monkeypatch.setattr(oracle, "residual_add",
+                        lambda P, R: 2.0 * (np.asarray(P) / 2.0 +
+                                            np.asarray(R)))
+    with pytest.raises(AssertionError):
+        test_residual_add_closes_the_layer()
