@@ -57,15 +57,19 @@ __device__ __forceinline__ float residual_at(const SkinnyArgs &g, int m,
                : static_cast<const float *>(g.res)[off];
 }
 
-// NORM: the activation rows are RMS-normalised on the fly (the normalisation
-// step of the decode layer fused into the product): each activation chunk
-// is multiplied by the matching chunk of the normalisation weights nw and
-// rounded to bf16 before the contraction, the lanes accumulate the squares
-// of the raw activations, and every output of row m is multiplied by
-// 1 / sqrt(mean_k x[m, k]^2 + eps).  Every activation element of a row is
-// loaded by exactly one lane of one wavefront of the program, so the
-// program holds the whole row's sum of squares after its reduction.
-template <int WDT, int KS, bool CBF16, int RT, bool NORM>
+// NORM (1 or 2): the activation rows are RMS-normalised on the fly (the
+// normalisation step of the decode layer fused into the product): each
+// activation chunk is multiplied by the matching chunk of the normalisation
+// weights nw and rounded to bf16 before the contraction, the lanes
+// accumulate the squares of the raw activations, and every output of row m
+// is multiplied by 1 / sqrt(mean_k x[m, k]^2 + eps).  Every activation
+// element of a row is loaded by exactly one lane of one wavefront of the
+// program, so the program holds the whole row's sum of squares after its
+// reduction.  NORM = 2 first copies the program's slice of nw into LDS and
+// reads each chunk from there when it is needed; NORM = 1 (slices longer
+// than the LDS budget) loads nw chunks into registers beside the
+// activation chunks, which costs a third more registers per lane.
+template <int WDT, int KS, bool CBF16, int RT, int NORM>
 __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
                                             const void *nw, float eps) {
     // Elements of K covered by one 16-byte weight load per lane group:
@@ -76,6 +80,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     constexpr int UNROLL = 8 / RT;
     __shared__ f32x4 part[KS][RT][64];
     __shared__ float ssq[NORM ? KS : 1][64];
+    extern __shared__ uint4 nw_lds[];   // NORM == 2: this program's nw
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n0 = blockIdx.x * 16 * RT;
@@ -119,7 +124,20 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     // 512 threads per program.
     constexpr int NB = KS <= 8 ? 2 : 1;
     uint4 wv[NB][UNROLL][RT], xv[NB][UNROLL][XV];
-    uint4 nv[NORM ? NB : 1][NORM ? UNROLL : 1][NORM ? XV : 1];
+    uint4 nv[NORM == 1 ? NB : 1][NORM == 1 ? UNROLL : 1][NORM == 1 ? XV : 1];
+    const int kb = sb * KSTEP;   // first element of this program's K range
+    int s0 = 0;                  // first K step of the buffer contracted
+    // NORM == 2: nw[kb, kb + (se - sb) KSTEP) into LDS as 16-byte chunks,
+    // zeros past K; run after the first weight loads are issued, so that
+    // its round trip overlaps theirs
+    auto stage_nw = [&]() {
+        if constexpr (NORM == 2) {
+            const int chunks = (se - sb) * KSTEP / 8;
+            for (int i = threadIdx.x; i < chunks; i += KS * 64)
+                nw_lds[i] = ld_chunk(NWc, kb + 8 * i, g.K, 8, 2);
+            __syncthreads();
+        }
+    };
     auto load_fast = [&](int s0, int b) {
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
@@ -130,7 +148,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 #pragma unroll
             for (int c = 0; c < XV; ++c) {
                 xv[b][u][c] = ld16(Xc + (int64_t)(k + 8 * c) * 2);
-                if constexpr (NORM)
+                if constexpr (NORM == 1)
                     nv[b][u][c] = ld16(NWc + (int64_t)(k + 8 * c) * 2);
             }
         }
@@ -149,7 +167,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             for (int c = 0; c < XV; ++c) {
                 xv[b][u][c] = ok ? ld_chunk(Xc, k + 8 * c, g.K, 8, 2)
                                  : uint4{0, 0, 0, 0};
-                if constexpr (NORM)
+                if constexpr (NORM == 1)
                     nv[b][u][c] = ok ? ld_chunk(NWc, k + 8 * c, g.K, 8, 2)
                                      : uint4{0, 0, 0, 0};
             }
@@ -176,13 +194,24 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
         }
         return uint4{o[0], o[1], o[2], o[3]};
     };
+    // buffer b holds the K steps s0 .. s0 + UNROLL - 1 (s0 as it stands
+    // at every call below)
     auto contract = [&](int b) {
-        if constexpr (NORM) {
+        if constexpr (NORM == 1) {
 #pragma unroll
             for (int u = 0; u < UNROLL; ++u)
 #pragma unroll
                 for (int c = 0; c < XV; ++c)
                     xv[b][u][c] = normed(xv[b][u][c], nv[b][u][c]);
+        } else if constexpr (NORM == 2) {
+#pragma unroll
+            for (int u = 0; u < UNROLL; ++u) {
+                const int k = (s0 + u) * KSTEP + grp * EPL;
+#pragma unroll
+                for (int c = 0; c < XV; ++c)
+                    xv[b][u][c] = normed(xv[b][u][c],
+                                         nw_lds[(k - kb) / 8 + c]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u)
@@ -210,10 +239,11 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     // steps of this program wholly inside K (split boundaries fall on
     // super-step boundaries, so only the last split has a ragged tail)
     const int nfull = min(g.K / KSTEP, se);
-    int s0 = sb + wave * UNROLL;
+    s0 = sb + wave * UNROLL;
     if constexpr (NB == 2) {
         bool have0 = s0 + UNROLL <= nfull;
         if (have0) load_fast(s0, 0);
+        stage_nw();
         while (have0) {
             const int s1 = s0 + STRIDE;
             const bool have1 = s1 + UNROLL <= nfull;
@@ -228,6 +258,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
             s0 = s2;
         }
     } else {
+        stage_nw();
         for (; s0 + UNROLL <= nfull; s0 += STRIDE) {
             load_fast(s0, 0);
             contract(0);
@@ -316,13 +347,16 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 
 template <int WDT, int KS, bool CBF16, int RT>
 __global__ __launch_bounds__(KS * 64) void gemm_skinny_kernel(SkinnyArgs g) {
-    skinny_body<WDT, KS, CBF16, RT, false>(g, nullptr, 0.f);
+    skinny_body<WDT, KS, CBF16, RT, 0>(g, nullptr, 0.f);
 }
 
-template <int WDT, int KS, bool CBF16, int RT>
-__global__ __launch_bounds__(KS * 64) void gemm_skinny_norm_kernel(
+// (bf16 weights, staged nw: three wavefronts per SIMD, as the plain bf16
+// product runs; the staged variant fits the register budget for it)
+template <int WDT, int KS, bool CBF16, int RT, int NORM>
+__global__ __launch_bounds__(KS * 64) __attribute__((amdgpu_waves_per_eu(
+    NORM == 2 && WDT == TG_BF16 ? 3 : 1))) void gemm_skinny_norm_kernel(
     SkinnyNormArgs a) {
-    skinny_body<WDT, KS, CBF16, RT, true>(a.s, a.norm_w, a.eps);
+    skinny_body<WDT, KS, CBF16, RT, NORM>(a.s, a.norm_w, a.eps);
 }
 
 // Merge of a split product: program p owns sub-tensor p of y (M rows x bn
@@ -391,6 +425,9 @@ hipError_t launch_bn(int c_bf16, int bn, int ksplit, const SkinnyArgs &a,
     return hipErrorInvalidValue;
 }
 
+// LDS budget of the staged normalisation weights (one program's K range)
+constexpr size_t kNormLdsMax = 32768;
+
 template <int WDT, int RT>
 hipError_t launch_norm_rt(int c_bf16, int ksplit, const SkinnyNormArgs &a,
                           hipStream_t st) {
@@ -398,12 +435,23 @@ hipError_t launch_norm_rt(int c_bf16, int ksplit, const SkinnyNormArgs &a,
     // the fused normalisation runs with four wavefronts per program
     if (ksplit != 4) return hipErrorInvalidValue;
     dim3 block(4 * 64);
-    if (c_bf16)
-        hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, true, RT>), grid,
-                           block, 0, st, a);
-    else
-        hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, false, RT>), grid,
-                           block, 0, st, a);
+    constexpr int KSTEP = WDT == TG_BF16 ? 32 : 64;
+    const size_t lds = (size_t)a.s.steps_per_split * KSTEP * 2;
+    if (lds <= kNormLdsMax) {
+        if (c_bf16)
+            hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, true, RT, 2>),
+                               grid, block, lds, st, a);
+        else
+            hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, false, RT, 2>),
+                               grid, block, lds, st, a);
+    } else {
+        if (c_bf16)
+            hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, true, RT, 1>),
+                               grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((gemm_skinny_norm_kernel<WDT, 4, false, RT, 1>),
+                               grid, block, 0, st, a);
+    }
     return hipGetLastError();
 }
 
