@@ -79,16 +79,16 @@ __device__ __forceinline__ f32x4 e4m3x4_to_f32(uint32_t w) {
 }
 
 // Four OCP E4M3 codes -> four bf16 (two dwords), exact: every E4M3 value is
-// a bf16 value.
+// a bf16 value.  The gfx950 scaled conversion turns two codes into two bf16
+// in one instruction; with the scale 1 it is the plain decode.
 __device__ __forceinline__ uint2 e4m3x4_to_bf16x4(uint32_t w) {
-    f32x4 f = e4m3x4_to_f32(w);
-    // exact values, so truncation of the low half is exact as well
-    float f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3];
-    uint32_t a = as_u32(f0) >> 16;
-    uint32_t b = as_u32(f1) & 0xffff0000u;
-    uint32_t c = as_u32(f2) >> 16;
-    uint32_t d = as_u32(f3) & 0xffff0000u;
-    return uint2{a | b, c | d};
+    typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+    const bf16x2_t lo = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w, 1.0f,
+                                                                 false);
+    const bf16x2_t hi = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w, 1.0f,
+                                                                 true);
+    return uint2{__builtin_bit_cast(uint32_t, lo),
+                 __builtin_bit_cast(uint32_t, hi)};
 }
 
 __device__ __forceinline__ uint4 ld16(const void *p) {
