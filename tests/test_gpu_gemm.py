@@ -831,10 +831,13 @@ def test_every_bf16_variant_normal_inputs(M, N, K, b_trans):
 
 
 @pytest.mark.parametrize("M,N,K", [(300, 264, 192), (4352, 4352, 128),
-                                   (200, 136, 0)])
+                                   (200, 136, 0), (300, 264, 704),
+                                   (4352, 4352, 640)])
 def test_every_fp8_variant(M, N, K):
     """E4M3: small integers bit-exact, scaled N(0,1) within the bar, for
-    every tiled configuration."""
+    every tiled configuration.  K of five or six 128-deep tiles (the last
+    one partial) reaches the L2 warm-up of the lock-step schedule, and
+    4352^2 has more sub-tensors than programs."""
     f8 = torch.float8_e4m3fn
     ia, ib, iad, ibd = _operands(
         M, N, K, True, lambda s: synth.small_int(s, 67).to(f8),
