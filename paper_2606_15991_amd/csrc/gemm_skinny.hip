@@ -3,8 +3,10 @@
 // of W, i.e. per output column).
 //
 // The work is bound by streaming W from HBM once (arithmetic intensity about
-// M flop per weight byte).  One tile program owns 16 or 32 output columns
-// (RT row tiles of 16 weight rows) for all M rows; its KS wavefronts split
+// M flop per weight byte).  One tile program owns bn <= 16 RT output columns
+// (RT row tiles of 16 weight rows, the rows past its bn repeating its last
+// row) for all M rows, so that bn can divide N into a whole number of
+// programs per compute unit; its KS wavefronts split
 // K between them and stream their share of the weight rows with 16-byte
 // loads, several in flight per lane.  With two row tiles every activation
 // chunk loaded serves two weight chunks.  The contraction runs on the 16x16x32 bf16 matrix
@@ -83,7 +85,8 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     extern __shared__ uint4 nw_lds[];   // NORM == 2: this program's nw
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n0 = blockIdx.x * 16 * RT;
+    const int n0 = blockIdx.x * g.bn;
+    const int n_end = min(n0 + g.bn, g.N);   // this program's columns
     const int r = lane & 15, grp = lane >> 4;
     const bool xrow_ok = r < g.M;
     const int xrow = xrow_ok ? r : 0;
@@ -92,7 +95,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 #pragma unroll
     for (int t = 0; t < RT; ++t) {
         int wrow = n0 + 16 * t + r;
-        wrow = wrow < g.N ? wrow : g.N - 1;
+        wrow = wrow < n_end ? wrow : n_end - 1;
         W[t] = static_cast<const char *>(g.w) +
                (int64_t)wrow * g.ldw * (WDT == TG_BF16 ? 2 : 1);
     }
@@ -115,8 +118,9 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
     // UNROLL weight and activation chunks of a super-step are loaded before
     // any is contracted, so every lane has UNROLL weight loads in flight
     // (the other wavefronts of the SIMD overlap their own).  Super-steps
-    // wholly inside K load without bounds tests: rows beyond N were clamped
-    // to row N - 1 and activation rows beyond M read row 0, and both only
+    // wholly inside K load without bounds tests: rows beyond the program's
+    // columns were clamped to its last row (the repeated loads hit the same
+    // cache lines) and activation rows beyond M read row 0, and both only
     // feed outputs that are never stored.  A ragged K tail takes the checked
     // loads.
     // Two register buffers (the wave's next super-step is loaded while the
@@ -303,7 +307,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int n = n0 + 16 * t + 4 * grp + v;
-                if (n < g.N) dst[n] = s[v];
+                if (n < n_end) dst[n] = s[v];
             }
         }
         return;
@@ -330,7 +334,7 @@ __device__ __forceinline__ void skinny_body(const SkinnyArgs &g,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int n = n0 + 16 * t + 4 * grp + v;
-            if (n < g.N) {
+            if (n < n_end) {
                 float y = s[v] * sa;
                 if (g.scale_w) y *= g.scale_w[n];
                 if (g.res) y += residual_at(g, m, n);
@@ -394,7 +398,7 @@ __global__ __launch_bounds__(256) void skinny_merge_kernel(SkinnyArgs g,
 
 template <int WDT, int KS, int RT>
 hipError_t launch_ks(int c_bf16, const SkinnyArgs &a, hipStream_t st) {
-    dim3 grid((a.N + 16 * RT - 1) / (16 * RT), a.splitk), block(KS * 64);
+    dim3 grid((a.N + a.bn - 1) / a.bn, a.splitk), block(KS * 64);
     if (c_bf16)
         hipLaunchKernelGGL((gemm_skinny_kernel<WDT, KS, true, RT>), grid,
                            block, 0, st, a);
@@ -420,9 +424,9 @@ hipError_t launch_w(int c_bf16, int ksplit, const SkinnyArgs &a,
 template <int WDT>
 hipError_t launch_bn(int c_bf16, int bn, int ksplit, const SkinnyArgs &a,
                      hipStream_t st) {
-    if (bn == 16) return launch_w<WDT, 1>(c_bf16, ksplit, a, st);
-    if (bn == 32) return launch_w<WDT, 2>(c_bf16, ksplit, a, st);
-    return hipErrorInvalidValue;
+    if (bn != a.bn || bn < 1 || bn > 32) return hipErrorInvalidValue;
+    if (bn <= 16) return launch_w<WDT, 1>(c_bf16, ksplit, a, st);
+    return launch_w<WDT, 2>(c_bf16, ksplit, a, st);
 }
 
 // LDS budget of the staged normalisation weights (one program's K range)
@@ -431,7 +435,7 @@ constexpr size_t kNormLdsMax = 32768;
 template <int WDT, int RT>
 hipError_t launch_norm_rt(int c_bf16, int ksplit, const SkinnyNormArgs &a,
                           hipStream_t st) {
-    dim3 grid((a.s.N + 16 * RT - 1) / (16 * RT), a.s.splitk);
+    dim3 grid((a.s.N + a.s.bn - 1) / a.s.bn, a.s.splitk);
     // the fused normalisation runs with four wavefronts per program
     if (ksplit != 4) return hipErrorInvalidValue;
     dim3 block(4 * 64);
@@ -458,9 +462,9 @@ hipError_t launch_norm_rt(int c_bf16, int ksplit, const SkinnyNormArgs &a,
 template <int WDT>
 hipError_t launch_norm_w(int c_bf16, int bn, int ksplit,
                          const SkinnyNormArgs &a, hipStream_t st) {
-    if (bn == 16) return launch_norm_rt<WDT, 1>(c_bf16, ksplit, a, st);
-    if (bn == 32) return launch_norm_rt<WDT, 2>(c_bf16, ksplit, a, st);
-    return hipErrorInvalidValue;
+    if (bn != a.s.bn || bn < 1 || bn > 32) return hipErrorInvalidValue;
+    if (bn <= 16) return launch_norm_rt<WDT, 1>(c_bf16, ksplit, a, st);
+    return launch_norm_rt<WDT, 2>(c_bf16, ksplit, a, st);
 }
 
 }  // namespace

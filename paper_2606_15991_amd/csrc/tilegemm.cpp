@@ -317,10 +317,23 @@ struct SkinnyGeo {
 SkinnyGeo skinny_geo(const Problem &p, int bn) {
     SkinnyGeo g;
     g.kstep = p.b_dt == TG_BF16 ? 32 : 64;
-    g.unroll = 8 / (bn / 16);
+    g.unroll = bn > 16 ? 4 : 8;   // two row tiles: four K steps of two
     g.nsteps = (p.K + g.kstep - 1) / g.kstep;
     g.supers = (g.nsteps + g.unroll - 1) / g.unroll;
     return g;
+}
+
+// Decode columns per program that deal N evenly over whole rounds of the
+// compute units: N / (ncu r) for the fewest rounds r that bring it to at
+// most 32 columns and divide N exactly (else ceil(N / (ncu r)) for the
+// fewest rounds); 0 where that leaves fewer than 8 columns per program.
+int32_t balanced_bn(int64_t N, int64_t ncu) {
+    const int64_t r0 = (N + 32 * ncu - 1) / (32 * ncu);
+    for (int64_t r = r0; r < r0 + 4; ++r)
+        if (N % (ncu * r) == 0 && N / (ncu * r) >= 8)
+            return (int32_t)(N / (ncu * r));
+    const int64_t bn = (N + ncu * r0 - 1) / (ncu * r0);
+    return bn >= 8 && bn <= 32 ? (int32_t)bn : 0;
 }
 
 // Splits that get K work when `splitk` are asked for: each split takes
@@ -371,7 +384,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
     bool s_ok = np == 1 && skinny_ok(p, A, B);
     if (cfg.kind == TG_KIND_AUTO) {
         if (s_ok && (cfg.bm == 0 || (cfg.bm >= p.M && cfg.bm <= 16)) &&
-            (cfg.bn == 0 || cfg.bn == 16 || cfg.bn == 32))
+            cfg.bn >= 0 && cfg.bn <= 32)
             cfg.kind = TG_KIND_SKINNY;
         else if (t_ok && (cfg.bm == 0 ||
                           find_variant(L.gemm_dt, cfg.bm, cfg.bn, cfg.wm,
@@ -395,6 +408,17 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         // the decode defaults assume MI355X's 256 compute units where the
         // device cannot be asked (host-only planning)
         const int64_t ncu = cus > 0 ? cus : 256;
+        // One round of programs, one per compute unit: where N / ncu is 8 to
+        // 32 columns, programs of that many columns fill the machine with
+        // no K split and so no merge launch.  Measured on (M, N, K) =
+        // (1 and 8, 5120, 5120) and (1, 5120, 25600), bf16 and e4m3 cold
+        // weights: 3.5-17 % faster than 16-column programs with the best
+        // K split (for (1, 51200, 5120), eight rounds of 25 columns lose
+        // to 16-column programs, so only the one-round case takes it).
+        const int32_t bal = balanced_bn(p.N, ncu);
+        const bool one_round = cfg.bn == 0 && cfg.splitk <= 1 && bal > 0 &&
+                               p.N <= 32 * ncu;
+        if (one_round) cfg.bn = bal;
         if (cfg.bn == 0) {
             // 32-column programs (each activation chunk serves two weight
             // rows) for e4m3 weights with several activation rows or long
@@ -404,9 +428,9 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
                 (p.M > 4 || (p.N + 15) / 16 >= 4 * ncu);
             cfg.bn = wide ? 32 : 16;
         }
-        if (cfg.bm < p.M || cfg.bm > 16 || (cfg.bn != 16 && cfg.bn != 32))
+        if (cfg.bm < p.M || cfg.bm > 16 || cfg.bn < 1 || cfg.bn > 32)
             return fail(TG_E_UNSUPPORTED,
-                        "decode kernel owns 16-row x 16- or 32-column "
+                        "decode kernel owns 16-row x 1..32-column "
                         "sub-tensors (partition %d x %d)", cfg.bm, cfg.bn);
         cfg.bm = 16;
         const SkinnyGeo geo = skinny_geo(p, cfg.bn);
@@ -419,7 +443,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             // and 8, bf16 and e4m3, cold weights): within 3 % of the best
             // configuration of each shape on average.
             int64_t sk = 1;
-            while (sk < 8 && progs * sk < 4 * ncu &&
+            while (!one_round && sk < 8 && progs * sk < 4 * ncu &&
                    (geo.supers + 2 * sk - 1) / (2 * sk) >= 4)
                 sk *= 2;
             while (sk > 1 &&
@@ -441,6 +465,10 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             // of loads in flight.
             int ks = 4;
             while (ks < 16 && progs * cfg.splitk * ks < ncu) ks *= 2;
+            // one round of programs: eight wavefronts for e4m3 weights
+            // (half the bytes per K element; measured 3-9 % faster than
+            // four), four for bf16
+            if (one_round && p.b_dt == TG_FP8_E4M3) ks = 8;
             // no more wavefronts than super-steps of K (eight 16-byte
             // weight loads per lane each) in one split
             while (ks > 1 && ks > per) ks /= 2;
@@ -562,11 +590,15 @@ void candidates(const Problem &p, const tg_in *A, const tg_in *B,
     const int np = p.precision == TG_PREC_BF16X3 ? 3
                    : p.precision == TG_PREC_BF16X6 ? 6 : 1;
     const int gdt = np > 1 ? TG_BF16 : p.a_dt;
-    for (int bn : {16, 32})
+    const int cus = device_cus();
+    const int32_t bal = balanced_bn(p.N, cus > 0 ? cus : 256);
+    // 16- and 32-column programs, and the column count that deals N evenly
+    // over the compute units
+    for (int bn : {16, 32, bal == 16 || bal == 32 ? 0 : bal})
         for (int sk : {1, 2, 4, 8})
             for (int ks : {1, 2, 4, 8, 16}) {
                 // K split over programs with two to eight wavefronts each
-                if (sk > 1 && (ks < 2 || ks > 8)) continue;
+                if (bn == 0 || (sk > 1 && (ks < 2 || ks > 8))) continue;
                 tg_config c{};
                 c.kind = TG_KIND_SKINNY;
                 c.bn = bn;

@@ -362,27 +362,43 @@ def test_picker_features_describe_the_configuration():
 
 def test_decode_default_configuration():
     """Without a GPU the plan still resolves the decode kernel's defaults
-    (for 256 compute units): 16-column programs, 32 for e4m3 weights with
-    more than four activation rows or more than 4 x 256 16-column
-    programs; K split over programs (given a workspace) until there are
-    four programs per compute unit while every split keeps four
-    super-steps; four wavefronts split each program's K."""
-    cases = (  # wdt, M, N, K, bn, splitk
-        (torch.bfloat16, 1, 5120, 5120, 16, 4),
-        (torch.bfloat16, 8, 5120, 5120, 16, 4),
-        (torch.bfloat16, 1, 51200, 5120, 16, 1),
-        (torch.bfloat16, 1, 5120, 25600, 16, 4),
-        (torch.float8_e4m3fn, 1, 5120, 5120, 16, 2),
-        (torch.float8_e4m3fn, 8, 5120, 5120, 32, 4),
-        (torch.float8_e4m3fn, 1, 51200, 5120, 32, 1),
-        (torch.float8_e4m3fn, 8, 5120, 25600, 32, 8))
-    for wdt, M, N, K, bn, sk in cases:
+    (for 256 compute units): where N / 256 is 8 to 32 columns, one round
+    of 256 programs of that many columns with no K split (eight wavefronts
+    for e4m3 weights, four for bf16); otherwise 16-column programs, 32 for
+    e4m3 weights with more than four activation rows or more than 4 x 256
+    16-column programs, K split over programs (given a workspace) until
+    there are four programs per compute unit while every split keeps four
+    super-steps, four wavefronts splitting each program's K."""
+    cases = (  # wdt, M, N, K, bn, ksplit, splitk
+        (torch.bfloat16, 1, 5120, 5120, 20, 4, 1),
+        (torch.bfloat16, 8, 5120, 5120, 20, 4, 1),
+        (torch.bfloat16, 1, 51200, 5120, 16, 4, 1),
+        (torch.bfloat16, 1, 5120, 25600, 20, 4, 1),
+        (torch.bfloat16, 1, 1040, 4096, 16, 4, 4),
+        (torch.bfloat16, 1, 3000, 4096, 12, 4, 1),
+        (torch.bfloat16, 1, 9000, 4096, 16, 4, 2),
+        (torch.float8_e4m3fn, 1, 5120, 5120, 20, 8, 1),
+        (torch.float8_e4m3fn, 8, 5120, 5120, 20, 8, 1),
+        (torch.float8_e4m3fn, 1, 51200, 5120, 32, 4, 1),
+        (torch.float8_e4m3fn, 8, 5120, 25600, 20, 8, 1),
+        (torch.float8_e4m3fn, 8, 1040, 25600, 32, 4, 8))
+    for wdt, M, N, K, bn, ks, sk in cases:
         x = torch.empty((M, K), dtype=torch.bfloat16)
         W = torch.empty((N, K), dtype=wdt)
         y = torch.empty((M, N), dtype=torch.bfloat16)
-        cfg = tg.tile_gemm_plan(x, W, y, b_trans=True, want_map=False)[0]
+        cfg, n_prog = tg.tile_gemm_plan(x, W, y, b_trans=True,
+                                        want_map=False)[:2]
         assert (cfg["kind"], cfg["bn"], cfg["ksplit"], cfg["splitk"]) == \
-            (tg.TG_KIND_SKINNY, bn, 4, sk), (wdt, M, N, K, cfg)
+            (tg.TG_KIND_SKINNY, bn, ks, sk), (wdt, M, N, K, cfg)
+        assert n_prog == -(-N // bn)
+    # the one-round columns deal N exactly where 256 divides it
+    x = torch.empty((1, 4096), dtype=torch.bfloat16)
+    for N, bn in ((2048, 8), (4096, 16), (8192, 32), (7936, 31)):
+        W = torch.empty((N, 4096), dtype=torch.bfloat16)
+        y = torch.empty((1, N), dtype=torch.bfloat16)
+        cfg, n_prog = tg.tile_gemm_plan(x, W, y, b_trans=True,
+                                        want_map=False)[:2]
+        assert (cfg["bn"], cfg["splitk"], n_prog) == (bn, 1, 256), (N, cfg)
     # short rows: no more wavefronts than K has super-steps (256 bf16)
     for K, ks in ((64, 1), (520, 2), (1024, 4)):
         x = torch.empty((8, K), dtype=torch.bfloat16)

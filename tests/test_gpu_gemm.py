@@ -261,6 +261,35 @@ def test_decode_split_k_bit_exact_and_deterministic(sk, wdt):
     assert rel_err(C1.cpu(), reference(xn.cpu(), Wn.cpu(), True)) <= 1e-5
 
 
+@pytest.mark.parametrize("bn", [1, 5, 11, 17, 20, 31])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+def test_decode_any_column_count_bit_exact(bn, wdt):
+    """Programs owning any number of output columns up to 32 (the weight
+    rows past a program's columns repeat its last row and are never
+    stored): small-integer operands give the oracle's values exactly and
+    each element is stored once, for the plain launch and the K split with
+    its merge; ragged N and K."""
+    M, N, K = 3, 203, 1552     # K: 48.5 bf16 and 24.25 e4m3 K steps
+    note("decode columns", bn, wdt)
+    dt = torch.bfloat16 if wdt == "bf16" else torch.float8_e4m3fn
+    x = synth.to_bf16(synth.small_int((M, K), 49))
+    W = synth.small_int((N, K), 50).to(dt)
+    xd, Wd = dev_padded(x), dev_padded(W)
+    R = reference(x, W, True)
+    for sk in (1, 3):
+        cfg = {"kind": "skinny", "bn": bn, "ksplit": 4, "splitk": sk}
+        for out in (torch.float32, torch.bfloat16):
+            C = torch.full((M, N), float("nan"), dtype=out, device=DEV)
+            wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+            tg.tile_gemm(xd, Wd, C, b_trans=True, config=cfg, write_count=wc)
+            torch.cuda.synchronize()
+            assert tuple(tg.tile_gemm.last_partition) == (16, bn)
+            assert torch.all(wc == 1), (cfg, out)
+            want = R if out == torch.float32 else exact64(
+                torch.from_numpy(R).to(torch.bfloat16))
+            assert np.array_equal(exact64(C.cpu()), want), (cfg, out)
+
+
 def test_decode_weight_only_fp8_end_to_end_error():
     """Weight-only E4M3 against the unquantised binary64 product: the
     quantisation error of N(0, 0.02) weights, K = 5120, stays within 3e-2."""
@@ -688,11 +717,14 @@ def test_decode_ragged_k(M, K, wdt):
 
 
 @pytest.mark.parametrize("M,N,K", [(1, 200, 1000), (8, 1040, 4096),
-                                   (16, 80, 512), (3, 72, 1001)])
+                                   (16, 80, 512), (3, 72, 1001),
+                                   (2, 2600, 520)])
 @pytest.mark.parametrize("wdt", ["bf16", "fp8"])
 def test_every_decode_variant(M, N, K, wdt):
-    """Every decode configuration (16- or 32-column programs, every K split)
-    within the binary32 bar against the oracle, each element stored once."""
+    """Every decode configuration (16- and 32-column programs, and for
+    N = 2600 the 11-column programs of one round over 256 compute units;
+    every K split) within the binary32 bar against the oracle, each element
+    stored once."""
     if wdt == "fp8" and K % 16:
         K += 16 - K % 16
     x = synth.to_bf16(synth.normal((M, K), 47))
@@ -707,7 +739,9 @@ def test_every_decode_variant(M, N, K, wdt):
     C = torch.empty((M, N), device=DEV)
     cfgs = [c for c in tg.tile_gemm_candidates(xd, Wd, C, b_trans=True)
             if c["kind"] == tg.TG_KIND_SKINNY]
-    assert sorted({c["bn"] for c in cfgs}) == [16, 32]
+    assert {16, 32} <= {c["bn"] for c in cfgs}
+    if N == 2600:
+        assert 11 in {c["bn"] for c in cfgs}
     for cfg in cfgs:
         note("every decode", M, N, K, wdt, cfg)
         C.fill_(float("nan"))
