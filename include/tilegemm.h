@@ -458,10 +458,13 @@ tg_status tile_error_norm(const void *C, int32_t c_dtype, const double *R,
  * ---------------------------------------------------------------------- */
 
 /*
- * tile_gemm_candidates -- every configuration tile_gemm accepts for these
- * arguments (honouring C's partition when it is set).  Writes up to `max`
- * into `out` (host) and returns the total count, or -1 on invalid arguments.
- * Host only.
+ * tile_gemm_candidates -- the configurations the autotuner and the picker
+ * choose among for these arguments (honouring C's partition when it is
+ * set): every tiled instantiation tile_gemm accepts, and for decode
+ * products 16- and 32-column programs plus the width that deals N evenly
+ * over whole rounds of the compute units, each with its wavefront counts
+ * and K splits.  Writes up to `max` into `out` (host) and returns the total
+ * count, or -1 on invalid arguments.  Host only.
  */
 int32_t tile_gemm_candidates(const tg_in *A, const tg_in *B, const tg_out *C,
                              const tg_opts *opts, tg_config *out, int32_t max);
