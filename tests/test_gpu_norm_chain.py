@@ -146,9 +146,10 @@ def test_fused_norm_matvec_small_integers_bit_exact(M, N, K, wdt, out,
         -2, 3, (N,), generator=g).float()
     y = torch.full((M, N), float("nan"), dtype=out, device=DEV)
     wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
-    # split=True: the library's default, which splits K over programs
-    # where that fills the chip (the workspace is allocated by the
-    # binding); split=False: no workspace, one program per sub-tensor
+    # split=True: the library's default given a workspace (allocated by
+    # the binding), which splits K over programs for N = 300 and 64 and
+    # runs one round of 20-column programs for N = 5120; split=False: no
+    # workspace, one program per sub-tensor
     tg.tile_rms_norm_matvec(x.to(DEV), nw.to(DEV), W.to(DEV), y, 0.0,
                             scale_w=None if sw is None else sw.to(DEV),
                             write_count=wc,
