@@ -290,6 +290,33 @@ def test_decode_any_column_count_bit_exact(bn, wdt):
             assert np.array_equal(exact64(C.cpu()), want), (cfg, out)
 
 
+@pytest.mark.parametrize("N,bn", [(2048, 8), (2600, 11), (7936, 31),
+                                  (8192, 32)])
+@pytest.mark.parametrize("wdt", ["bf16", "fp8"])
+def test_decode_one_round_default_bit_exact(N, bn, wdt):
+    """The default decode configuration where N / 256 is 8 to 32 columns:
+    one round of programs of that width, no K split.  Sixteen activation
+    rows (the most the decode kernel takes), small-integer operands, ragged
+    K: exact, each element stored once."""
+    M, K = 16, 1040
+    note("decode one round", N, bn, wdt)
+    dt = torch.bfloat16 if wdt == "bf16" else torch.float8_e4m3fn
+    x = synth.to_bf16(synth.small_int((M, K), 51))
+    W = synth.small_int((N, K), 52).to(dt)
+    xd, Wd = dev_padded(x), dev_padded(W)
+    C = torch.full((M, N), float("nan"), device=DEV)
+    wc = torch.zeros((M, N), dtype=torch.int32, device=DEV)
+    plan = tg.tile_gemm_plan(xd, Wd, C, b_trans=True, want_map=False,
+                             workspace_bytes=64 << 20)[0]
+    assert (plan["kind"], plan["bn"], plan["splitk"]) == \
+        (tg.TG_KIND_SKINNY, bn, 1), plan
+    tg.tile_gemm(xd, Wd, C, b_trans=True, write_count=wc)
+    torch.cuda.synchronize()
+    assert tuple(tg.tile_gemm.last_partition) == (16, bn)
+    assert torch.all(wc == 1)
+    assert np.array_equal(exact64(C.cpu()), reference(x, W, True))
+
+
 def test_decode_weight_only_fp8_end_to_end_error():
     """Weight-only E4M3 against the unquantised binary64 product: the
     quantisation error of N(0, 0.02) weights, K = 5120, stays within 3e-2."""
