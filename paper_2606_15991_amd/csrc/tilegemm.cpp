@@ -421,11 +421,12 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         if (one_round) cfg.bn = bal;
         if (cfg.bn == 0) {
             // 32-column programs (each activation chunk serves two weight
-            // rows) for e4m3 weights with several activation rows or long
-            // sweeps; measured on the decode shapes with cold weights
+            // rows) for e4m3 weights with more than four activation rows,
+            // or three or four over long sweeps; measured on the decode
+            // shapes with cold weights
             const bool wide =
                 p.b_dt == TG_FP8_E4M3 &&
-                (p.M > 4 || (p.N + 15) / 16 >= 4 * ncu);
+                (p.M > 4 || (p.M > 2 && (p.N + 15) / 16 >= 4 * ncu));
             cfg.bn = wide ? 32 : 16;
         }
         if (cfg.bm < p.M || cfg.bm > 16 || cfg.bn < 1 || cfg.bn > 32)
@@ -469,6 +470,14 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             // (half the bytes per K element; measured 3-9 % faster than
             // four), four for bf16
             if (one_round && p.b_dt == TG_FP8_E4M3) ks = 8;
+            // e4m3 weights, one or two activation rows, several programs
+            // per compute unit: two wavefronts per 16-column program
+            // (measured at (1 and 2, 51200, 5120), (1, 16384, 4096) and
+            // (1, 16384, 16384): 6-12 % faster than 32-column programs of
+            // four wavefronts; 4 % slower at (1, 32768, 4096))
+            if (!one_round && p.b_dt == TG_FP8_E4M3 && p.M <= 2 &&
+                cfg.bn == 16 && cfg.splitk == 1 && progs >= ncu)
+                ks = 2;
             // no more wavefronts than super-steps of K (eight 16-byte
             // weight loads per lane each) in one split
             while (ks > 1 && ks > per) ks /= 2;

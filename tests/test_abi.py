@@ -189,9 +189,10 @@ def test_plan_decode_and_simple_kinds():
     y = torch.empty((1, 51200), dtype=torch.bfloat16)
     cfg, n_prog, _, _ = tg.tile_gemm_plan(x, w, y, b_trans=True,
                                           want_map=False)
-    # 32-column programs by default for this long e4m3 sweep
-    assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["bn"] == 32
-    assert n_prog == 1600
+    # one activation row over a long e4m3 sweep: 16-column programs of two
+    # wavefronts
+    assert cfg["kind"] == tg.TG_KIND_SKINNY and cfg["bn"] == 16
+    assert cfg["ksplit"] == 2 and n_prog == 3200
     # K not a multiple of 8 bf16 elements -> no vector loads -> simple kernel
     cfg, n_prog, offs, tiles = _plan(100, 90, 37)
     assert cfg["kind"] == tg.TG_KIND_SIMPLE and n_prog == 2 * 2
@@ -365,10 +366,12 @@ def test_decode_default_configuration():
     (for 256 compute units): where N / 256 is 8 to 32 columns, one round
     of 256 programs of that many columns with no K split (eight wavefronts
     for e4m3 weights, four for bf16); otherwise 16-column programs, 32 for
-    e4m3 weights with more than four activation rows or more than 4 x 256
-    16-column programs, K split over programs (given a workspace) until
-    there are four programs per compute unit while every split keeps four
-    super-steps, four wavefronts splitting each program's K."""
+    e4m3 weights with more than four activation rows (or three or four
+    over more than 4 x 256 16-column programs), K split over programs
+    (given a workspace) until there are four programs per compute unit
+    while every split keeps four super-steps, four wavefronts splitting
+    each program's K (two for e4m3 weights with one or two activation
+    rows and at least one unsplit program per compute unit)."""
     cases = (  # wdt, M, N, K, bn, ksplit, splitk
         (torch.bfloat16, 1, 5120, 5120, 20, 4, 1),
         (torch.bfloat16, 8, 5120, 5120, 20, 4, 1),
@@ -379,7 +382,9 @@ def test_decode_default_configuration():
         (torch.bfloat16, 1, 9000, 4096, 16, 4, 2),
         (torch.float8_e4m3fn, 1, 5120, 5120, 20, 8, 1),
         (torch.float8_e4m3fn, 8, 5120, 5120, 20, 8, 1),
-        (torch.float8_e4m3fn, 1, 51200, 5120, 32, 4, 1),
+        (torch.float8_e4m3fn, 1, 51200, 5120, 16, 2, 1),
+        (torch.float8_e4m3fn, 4, 51200, 5120, 32, 4, 1),
+        (torch.float8_e4m3fn, 2, 16384, 4096, 16, 2, 1),
         (torch.float8_e4m3fn, 8, 5120, 25600, 20, 8, 1),
         (torch.float8_e4m3fn, 8, 1040, 25600, 32, 4, 8))
     for wdt, M, N, K, bn, ks, sk in cases:

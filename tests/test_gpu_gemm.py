@@ -189,9 +189,11 @@ def test_fp8_instruction_precision_characterised():
 # ------------------------------------------------------------------ decode
 
 def decode_bn(wdt, M, N=0):
-    """Output columns per decode program by default: 32 for e4m3 weights
-    with more than four activation rows (or very long sweeps), else 16."""
-    return 32 if wdt == "fp8" and (M > 4 or N >= 16 * 1024) else 16
+    """Output columns per decode program by default outside one round: 32
+    for e4m3 weights with more than four activation rows (or three or four
+    over very long sweeps), else 16."""
+    return 32 if wdt == "fp8" and (M > 4 or (M > 2 and N >= 16 * 1024)) \
+        else 16
 
 
 @pytest.mark.parametrize("M", [1, 8, 16])

@@ -126,7 +126,10 @@ def test_learned_picker_beats_default_and_tracks_exhaustive():
     hist = model["loss_history"]
     assert hist[-1][1] < 0.5 * hist[0][1]
     picker.install(model)
-    te = picker.collect(synth.picker_shapes(6, 80, hi=4096), pool, reps=5)
+    # held-out timings averaged over 20 launches: the exhaustive best is a
+    # minimum over 20-45 near-tied candidates on small shapes, so timing
+    # noise alone would pull every ratio below 1
+    te = picker.collect(synth.picker_shapes(6, 80, hi=4096), pool, reps=20)
     tg.tile_tune_cache_clear()
     ev = picker.evaluate(te, pool)
     s = picker.summarize(ev)
