@@ -418,7 +418,15 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         const int32_t bal = balanced_bn(p.N, ncu);
         const bool one_round = cfg.bn == 0 && cfg.splitk <= 1 && bal > 0 &&
                                p.N <= 32 * ncu;
-        if (one_round) cfg.bn = bal;
+        // Several rounds with more than four activation rows: programs of
+        // the even width and one wavefront each, so that all of them are
+        // resident at once (eight per compute unit at N = 51200) with no
+        // K split.  Measured at (8 and 16, 51200, 5120): 4-17 % faster
+        // than 16- or 32-column programs of four wavefronts, bf16 and
+        // e4m3; at (8, 16384 and 32768, 4096) within -14..+4 %.
+        const bool resident = cfg.bn == 0 && cfg.splitk <= 1 && bal > 0 &&
+                              !one_round && p.M > 4;
+        if (one_round || resident) cfg.bn = bal;
         if (cfg.bn == 0) {
             // 32-column programs (each activation chunk serves two weight
             // rows) for e4m3 weights with more than four activation rows,
@@ -444,7 +452,8 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             // and 8, bf16 and e4m3, cold weights): within 3 % of the best
             // configuration of each shape on average.
             int64_t sk = 1;
-            while (!one_round && sk < 8 && progs * sk < 4 * ncu &&
+            while (!one_round && !resident && sk < 8 &&
+                   progs * sk < 4 * ncu &&
                    (geo.supers + 2 * sk - 1) / (2 * sk) >= 4)
                 sk *= 2;
             while (sk > 1 &&
@@ -470,6 +479,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             // (half the bytes per K element; measured 3-9 % faster than
             // four), four for bf16
             if (one_round && p.b_dt == TG_FP8_E4M3) ks = 8;
+            if (resident) ks = 1;
             // e4m3 weights, one or two activation rows, several programs
             // per compute unit: two wavefronts per 16-column program
             // (measured at (1 and 2, 51200, 5120), (1, 16384, 4096) and

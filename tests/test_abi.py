@@ -371,7 +371,10 @@ def test_decode_default_configuration():
     (given a workspace) until there are four programs per compute unit
     while every split keeps four super-steps, four wavefronts splitting
     each program's K (two for e4m3 weights with one or two activation
-    rows and at least one unsplit program per compute unit)."""
+    rows and at least one unsplit program per compute unit).  With more
+    than four activation rows and several rounds: programs of the even
+    width (N / (256 r), e.g. 25 columns at N = 51200) of one wavefront
+    each, no K split."""
     cases = (  # wdt, M, N, K, bn, ksplit, splitk
         (torch.bfloat16, 1, 5120, 5120, 20, 4, 1),
         (torch.bfloat16, 8, 5120, 5120, 20, 4, 1),
@@ -384,6 +387,9 @@ def test_decode_default_configuration():
         (torch.float8_e4m3fn, 8, 5120, 5120, 20, 8, 1),
         (torch.float8_e4m3fn, 1, 51200, 5120, 16, 2, 1),
         (torch.float8_e4m3fn, 4, 51200, 5120, 32, 4, 1),
+        (torch.float8_e4m3fn, 8, 51200, 5120, 25, 1, 1),
+        (torch.bfloat16, 16, 51200, 5120, 25, 1, 1),
+        (torch.bfloat16, 8, 16384, 4096, 32, 1, 1),
         (torch.float8_e4m3fn, 2, 16384, 4096, 16, 2, 1),
         (torch.float8_e4m3fn, 8, 5120, 25600, 20, 8, 1),
         (torch.float8_e4m3fn, 8, 1040, 25600, 32, 4, 8))
