@@ -427,6 +427,19 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
         const bool resident = cfg.bn == 0 && cfg.splitk <= 1 && bal > 0 &&
                               !one_round && p.M > 4;
         if (one_round || resident) cfg.bn = bal;
+        // bf16 weights, up to four activation rows, K up to 8192: where the
+        // one-round width needs two row tiles (more than 16 columns), half
+        // of it in one row tile, two programs per compute unit of two
+        // wavefronts each (both resident).  Measured at N = 5120, 6144 and
+        // 8192 (K 4096-8192): 4-18 % faster; at (1, 5120, 25600) 9 %
+        // slower, and where the one-round width is 16 or less (N = 4096)
+        // 7 % slower, hence the bounds.  Not for the fused normalisation,
+        // whose programs each stage the normalisation weights of their K
+        // range: twice the programs cost more than they gain (decode
+        // layer 21.0 against 19.9 us).
+        const bool halves = one_round && !norm && p.b_dt == TG_BF16 &&
+                            p.M <= 4 && p.K <= 8192 && bal > 16;
+        if (halves) cfg.bn = (bal + 1) / 2;
         if (cfg.bn == 0) {
             // 32-column programs (each activation chunk serves two weight
             // rows) for e4m3 weights with more than four activation rows,
@@ -480,6 +493,7 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             // four), four for bf16
             if (one_round && p.b_dt == TG_FP8_E4M3) ks = 8;
             if (resident) ks = 1;
+            if (halves) ks = 2;
             // e4m3 weights, one or two activation rows, several programs
             // per compute unit: two wavefronts per 16-column program
             // (measured at (1 and 2, 51200, 5120), (1, 16384, 4096) and

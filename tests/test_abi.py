@@ -365,7 +365,9 @@ def test_decode_default_configuration():
     """Without a GPU the plan still resolves the decode kernel's defaults
     (for 256 compute units): where N / 256 is 8 to 32 columns, one round
     of 256 programs of that many columns with no K split (eight wavefronts
-    for e4m3 weights, four for bf16); otherwise 16-column programs, 32 for
+    for e4m3 weights, four for bf16; for bf16 weights with up to four
+    activation rows and K up to 8192, where that width exceeds 16 columns,
+    half of it with two wavefronts); otherwise 16-column programs, 32 for
     e4m3 weights with more than four activation rows (or three or four
     over more than 4 x 256 16-column programs), K split over programs
     (given a workspace) until there are four programs per compute unit
@@ -376,12 +378,14 @@ def test_decode_default_configuration():
     width (N / (256 r), e.g. 25 columns at N = 51200) of one wavefront
     each, no K split."""
     cases = (  # wdt, M, N, K, bn, ksplit, splitk
-        (torch.bfloat16, 1, 5120, 5120, 20, 4, 1),
+        (torch.bfloat16, 1, 5120, 5120, 10, 2, 1),
         (torch.bfloat16, 8, 5120, 5120, 20, 4, 1),
         (torch.bfloat16, 1, 51200, 5120, 16, 4, 1),
         (torch.bfloat16, 1, 5120, 25600, 20, 4, 1),
         (torch.bfloat16, 1, 1040, 4096, 16, 4, 4),
         (torch.bfloat16, 1, 3000, 4096, 12, 4, 1),
+        (torch.bfloat16, 4, 8192, 8192, 16, 2, 1),
+        (torch.bfloat16, 1, 6144, 4096, 12, 2, 1),
         (torch.bfloat16, 1, 9000, 4096, 16, 4, 2),
         (torch.float8_e4m3fn, 1, 5120, 5120, 20, 8, 1),
         (torch.float8_e4m3fn, 8, 5120, 5120, 20, 8, 1),
@@ -402,11 +406,12 @@ def test_decode_default_configuration():
         assert (cfg["kind"], cfg["bn"], cfg["ksplit"], cfg["splitk"]) == \
             (tg.TG_KIND_SKINNY, bn, ks, sk), (wdt, M, N, K, cfg)
         assert n_prog == -(-N // bn)
-    # the one-round columns deal N exactly where 256 divides it
-    x = torch.empty((1, 4096), dtype=torch.bfloat16)
+    # the one-round columns deal N exactly where 256 divides it (eight
+    # activation rows: no halving)
+    x = torch.empty((8, 4096), dtype=torch.bfloat16)
     for N, bn in ((2048, 8), (4096, 16), (8192, 32), (7936, 31)):
         W = torch.empty((N, 4096), dtype=torch.bfloat16)
-        y = torch.empty((1, N), dtype=torch.bfloat16)
+        y = torch.empty((8, N), dtype=torch.bfloat16)
         cfg, n_prog = tg.tile_gemm_plan(x, W, y, b_trans=True,
                                         want_map=False)[:2]
         assert (cfg["bn"], cfg["splitk"], n_prog) == (bn, 1, 256), (N, cfg)
