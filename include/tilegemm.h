@@ -241,9 +241,13 @@ tg_status tile_partition_check(const tg_in *ins, int32_t n_in,
  *   opts may be NULL (native precision, checked, picker).  Precision modes
  *   BF16X3/X6 need f32 A and B and a workspace of
  *   tile_gemm_workspace_size() bytes.  Decode products (M <= 16, B stored
- *   N x K) own sub-tensors of 16 rows x 1..32 columns: by default N / (the
- *   compute units) columns where that is 8..32, one program per compute
- *   unit and no K split; otherwise 16 or 32 columns, and K may be split
+ *   N x K) own sub-tensors of 16 rows x 1..32 columns.  By default the
+ *   width deals N evenly over the compute units with no K split where it
+ *   can: N / (the compute units) columns where that is 8..32 (half of it,
+ *   two programs per compute unit, for bf16 weights with up to four rows
+ *   and K <= 8192 when it exceeds 16), or, over several rounds with more
+ *   than four rows, an even width of single-wavefront programs all
+ *   resident at once; otherwise 16 or 32 columns, and K may be split
  *   over several programs per sub-tensor: an explicit config with
  *   splitk > 1 needs a workspace of tile_gemm_workspace_size() bytes
  *   (TG_E_WORKSPACE without one); the default configuration splits only
