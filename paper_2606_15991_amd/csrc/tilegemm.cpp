@@ -490,8 +490,11 @@ tg_status choose_explicit(const Problem &p, const tg_in *A, const tg_in *B,
             while (ks < 16 && progs * cfg.splitk * ks < ncu) ks *= 2;
             // one round of programs: eight wavefronts for e4m3 weights
             // (half the bytes per K element; measured 3-9 % faster than
-            // four), four for bf16
-            if (one_round && p.b_dt == TG_FP8_E4M3) ks = 8;
+            // four) except with more than four rows over long K ((8, 5120,
+            // 25600): four are 5 % faster), four for bf16
+            if (one_round && p.b_dt == TG_FP8_E4M3 &&
+                !(p.M > 4 && p.K > 8192))
+                ks = 8;
             if (resident) ks = 1;
             if (halves) ks = 2;
             // e4m3 weights, one or two activation rows, several programs

@@ -365,7 +365,8 @@ def test_decode_default_configuration():
     """Without a GPU the plan still resolves the decode kernel's defaults
     (for 256 compute units): where N / 256 is 8 to 32 columns, one round
     of 256 programs of that many columns with no K split (eight wavefronts
-    for e4m3 weights, four for bf16; for bf16 weights with up to four
+    for e4m3 weights unless more than four rows meet K > 8192, four for
+    bf16; for bf16 weights with up to four
     activation rows and K up to 8192, where that width exceeds 16 columns,
     half of it with two wavefronts); otherwise 16-column programs, 32 for
     e4m3 weights with more than four activation rows (or three or four
@@ -395,7 +396,8 @@ def test_decode_default_configuration():
         (torch.bfloat16, 16, 51200, 5120, 25, 1, 1),
         (torch.bfloat16, 8, 16384, 4096, 32, 1, 1),
         (torch.float8_e4m3fn, 2, 16384, 4096, 16, 2, 1),
-        (torch.float8_e4m3fn, 8, 5120, 25600, 20, 8, 1),
+        (torch.float8_e4m3fn, 8, 5120, 25600, 20, 4, 1),
+        (torch.float8_e4m3fn, 1, 5120, 25600, 20, 8, 1),
         (torch.float8_e4m3fn, 8, 1040, 25600, 32, 4, 8))
     for wdt, M, N, K, bn, ks, sk in cases:
         x = torch.empty((M, K), dtype=torch.bfloat16)
