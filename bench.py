@@ -365,6 +365,11 @@ def bench_decode(args, tg):
     distinct weight copies (more than the 256 MB Infinity Cache holds), warm
     = the same weights every launch."""
     out = []
+    # the memory the earlier sections cached goes back to the device first,
+    # so that the weight copies are laid out as in a process of their own
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
     # one workspace for the K split over programs, reused by every launch
     ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
     for wdt in ("bf16", "fp8"):
